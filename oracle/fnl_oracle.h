@@ -1,0 +1,84 @@
+/*
+ * fnl_oracle.h -- plain FP64 CPU oracle for the local-f_NL CMB map generator
+ * of Elsner & Wandelt, "Improved simulation of non-Gaussian temperature and
+ * polarization CMB maps".
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing on the product path includes, links or
+ * calls this code: it exists so that tests/, the smoke check and the CPU
+ * baseline leg of the benchmark have an independent, obviously correct
+ * reference.  It shares no code with the HIP library.
+ *
+ * Conventions (all arrays row-major, FP64):
+ *   alm index      idx(l, m) = l(l+1)/2 + m, 0 <= m <= l <= L,
+ *                  complex values interleaved (re, im); Im a_l0 is ignored.
+ *   harmonics      Y_lm = lambda_lm(cos theta) e^{i m phi}, orthonormal,
+ *                  Condon-Shortley phase; real fields keep m >= 0 only.
+ *   grid           Gauss-Legendre rings, x_k = cos theta_k descending (north
+ *                  to south), phi_j = 2 pi j / nphi, pixel weight
+ *                  omega_k * 2 pi / nphi.
+ *   filter         [L+1][N][N], row i = output shell, column j = input shell.
+ *   alpha, beta    [L+1][N]: temperature and E-mode real-space transfer
+ *                  tables evaluated at the nodes.
+ */
+#ifndef FNL_ORACLE_H
+#define FNL_ORACLE_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { ORC_MEAN_SAMPLE = 0, ORC_MEAN_ENSEMBLE = 1 };
+
+typedef struct {
+    int lmax;            /* L                                             */
+    int nshell;          /* N radial nodes                                */
+    int ntheta;          /* Gauss-Legendre rings                          */
+    int nphi;            /* pixels per ring                               */
+    int mean_mode;       /* ORC_MEAN_SAMPLE or ORC_MEAN_ENSEMBLE          */
+    const double *r;     /* [N] node radii                                */
+    const double *w;     /* [N] quadrature weights                        */
+    const double *filter;/* [L+1][N][N]                                   */
+    const double *alpha; /* [L+1][N]                                      */
+    const double *beta;  /* [L+1][N]                                      */
+} orc_problem;
+
+/* Gauss-Legendre nodes (descending) and weights of order n. 0 on success. */
+int orc_gl_grid(int n, double *x, double *w);
+
+/* lambda_lm(x) for all 0 <= m <= l <= L at one x, stored at idx(l, m). */
+void orc_lambda_all(int lmax, double x, double *lam);
+
+/* Synthesis of one band-limited real field onto the grid:
+ * map[k][j] = sum_{l,m} c_m Re[alm_lm lambda_lm(x_k) e^{i m phi_j}],
+ * c_0 = 1, c_m = 2.                                                      */
+void orc_synth(int lmax, int ntheta, int nphi, const double *x,
+               const double *alm, double *map);
+
+/* Analysis: alm_lm = sum_k omega_k (2 pi / nphi) sum_j map[k][j]
+ * lambda_lm(x_k) e^{-i m phi_j}.                                           */
+void orc_anal(int lmax, int ntheta, int nphi, const double *x,
+              const double *wq, const double *map, double *alm);
+
+/* Radial filter: phi[i][idx] = sum_j F_l[i][j] noise[j][idx] (Im of m = 0
+ * dropped).  noise, phi: [N][n_lm] complex.                               */
+void orc_filter(const orc_problem *P, const double *noise, double *phi);
+
+/* Forward map generator.  noise: [N][n_lm] complex.  Every output pointer
+ * may be NULL.  a*: [n_lm] complex.  phiL, phiNL: [N][n_lm] complex.
+ * mu: [N].  Returns 0, or -1 on invalid arguments.                          */
+int orc_forward(const orc_problem *P, const double *noise, double fnl,
+                double *aT, double *aE, double *aT_lin, double *aE_lin,
+                double *aT_nl, double *aE_nl,
+                double *phiL, double *phiNL, double *mu);
+
+/* Adjoint of orc_forward for a real loss.  gT, gE: cotangents
+ * dLoss/dRe a + i dLoss/dIm a, [n_lm] complex.  grad_n: [N][n_lm] complex,
+ * same convention, Im of m = 0 set to 0.  grad_fnl: one double.            */
+int orc_adjoint(const orc_problem *P, const double *noise, double fnl,
+                const double *gT, const double *gE,
+                double *grad_n, double *grad_fnl);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

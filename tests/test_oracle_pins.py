@@ -1,0 +1,353 @@
+"""Pins of the FP64 CPU oracle against things other than itself: library
+routines (numpy, scipy), closed forms, identities, exact Gaunt-integral brute
+force and the continuous radial integral of Eq. phi2alm_r."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, special
+
+from oracle import gaunt
+from paper_0909_0009_amd import inputs
+
+SQ4PI = math.sqrt(4 * math.pi)
+
+
+def nlm(L):
+    return (L + 1) * (L + 2) // 2
+
+
+def idx(l, m):
+    return l * (l + 1) // 2 + m
+
+
+def rand_alm(L, rng, scale=1.0):
+    a = (rng.standard_normal(nlm(L)) + 1j * rng.standard_normal(nlm(L))) * scale
+    ls, ms = inputs.lm_arrays(L)
+    a[ms == 0] = a[ms == 0].real
+    return a
+
+
+# ------------------------------------------------------------ grid
+
+@pytest.mark.parametrize("n", [1, 2, 3, 7, 49, 385, 1537])
+def test_gl_grid_matches_numpy(orc, n):
+    x, w = orc.gl_grid(n)
+    xr, wr = np.polynomial.legendre.leggauss(n)
+    order = np.argsort(-xr)
+    assert np.max(np.abs(x - xr[order])) < 1e-14
+    # numpy's own edge weights drift at large n; compare absolutely and let
+    # the exactness test below carry the precision
+    assert np.max(np.abs(w - wr[order])) < 1e-13
+    assert abs(w.sum() - 2.0) < 1e-13
+
+
+@pytest.mark.parametrize("n", [5, 49, 200])
+def test_gl_grid_polynomial_exactness(orc, n):
+    x, w = orc.gl_grid(n)
+    for p in range(0, 2 * n, max(1, n // 7)):
+        exact = 0.0 if p % 2 else 2.0 / (p + 1)
+        got = float(np.sum(w * x ** p))
+        assert abs(got - exact) < 1e-13, (p, got, exact)
+
+
+# ------------------------------------------------------- Legendre
+
+@pytest.mark.parametrize("x", [0.0, 0.3, -0.77, 0.999, 0.99999])
+def test_lambda_unsold_identity(orc, x):
+    L = 300
+    lam = orc.lambda_all(L, x)
+    ls, ms = inputs.lm_arrays(L)
+    c = np.where(ms == 0, 1.0, 2.0)
+    s = np.bincount(ls, weights=c * lam ** 2)
+    ref = (2 * np.arange(L + 1) + 1) / (4 * math.pi)
+    assert np.max(np.abs(s / ref - 1)) < 1e-12
+
+
+def test_lambda_m0_is_legendre(orc):
+    L = 60
+    for x in (0.1, -0.5, 0.93):
+        lam = orc.lambda_all(L, x)
+        for l in range(L + 1):
+            c = np.zeros(l + 1)
+            c[l] = 1.0
+            ref = math.sqrt((2 * l + 1) / (4 * math.pi)) * np.polynomial.legendre.legval(x, c)
+            assert abs(lam[idx(l, 0)] - ref) < 1e-13
+
+
+def test_lambda_matches_scipy_sph_harm(orc):
+    L = 20
+    for theta in (0.2, 1.1, 2.5):
+        lam = orc.lambda_all(L, math.cos(theta))
+        for l in range(L + 1):
+            for m in range(l + 1):
+                y = special.sph_harm_y(l, m, theta, 0.0)
+                assert abs(lam[idx(l, m)] - y.real) < 1e-13, (l, m)
+
+
+def test_lambda_gl_orthonormality(orc):
+    L = 24
+    x, w = orc.gl_grid(L + 1)
+    lam = np.array([orc.lambda_all(L, xi) for xi in x])    # [ring, idx]
+    for m in (0, 1, 7, 24):
+        cols = [idx(l, m) for l in range(m, L + 1)]
+        G = 2 * math.pi * (lam[:, cols] * w[:, None]).T @ lam[:, cols]
+        assert np.max(np.abs(G - np.eye(len(cols)))) < 1e-13
+
+
+def test_lambda_pole_ring_no_overflow(orc):
+    """At the most polar ring of the lmax = 1024 grid the plain recurrence
+    stays finite and still satisfies the addition theorem."""
+    L = 1024
+    x, _ = orc.gl_grid(inputs.min_ntheta(L))
+    lam = orc.lambda_all(L, x[0])
+    assert np.all(np.isfinite(lam))
+    ls, ms = inputs.lm_arrays(L)
+    s = np.bincount(ls, weights=np.where(ms == 0, 1.0, 2.0) * lam ** 2)
+    ref = (2 * np.arange(L + 1) + 1) / (4 * math.pi)
+    assert np.max(np.abs(s / ref - 1)) < 1e-11
+
+
+# ------------------------------------------------------ transforms
+
+def scipy_ring_synthesis(L, ntheta, nphi, alm):
+    """Independent synthesis: scipy Y_lm for G_m(theta), numpy irfft for phi."""
+    xr, _ = np.polynomial.legendre.leggauss(ntheta)
+    th = np.arccos(-xr)        # x descending = north to south
+    out = np.empty((ntheta, nphi))
+    for k, t in enumerate(th):
+        G = np.zeros(nphi // 2 + 1, dtype=complex)
+        for l in range(L + 1):
+            for m in range(l + 1):
+                a = alm[idx(l, m)]
+                if m == 0:
+                    a = a.real
+                G[m] += special.sph_harm_y(l, m, t, 0.0).real * a
+        out[k] = np.fft.irfft(G * nphi, nphi)
+    return out
+
+
+def test_synthesis_matches_scipy_numpy(orc):
+    L, nt, nph = 12, 19, 37
+    a = rand_alm(L, np.random.default_rng(1))
+    got = orc.synth(L, nt, nph, a)
+    ref = scipy_ring_synthesis(L, nt, nph, a)
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_analysis_matches_scipy_numpy(orc):
+    L, nt, nph = 10, 13, 31
+    rng = np.random.default_rng(2)
+    mp = rng.standard_normal((nt, nph))
+    got = orc.anal(L, nt, nph, mp)
+    xr, wr = np.polynomial.legendre.leggauss(nt)
+    xr, wr = xr[::-1], wr[::-1]
+    F = np.fft.rfft(mp, axis=1) * (2 * math.pi / nph)
+    ref = np.zeros(nlm(L), dtype=complex)
+    for k in range(nt):
+        t = math.acos(xr[k])
+        for l in range(L + 1):
+            for m in range(l + 1):
+                ref[idx(l, m)] += wr[k] * special.sph_harm_y(l, m, t, 0.0).real * F[k, m]
+    ls, ms = inputs.lm_arrays(L)
+    ref[ms == 0] = ref[ms == 0].real
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("L", [1, 8, 33])
+def test_round_trip_is_identity(orc, L):
+    a = rand_alm(L, np.random.default_rng(L))
+    nt, nph = L + 1, 2 * L + 1
+    back = orc.anal(L, nt, nph, orc.synth(L, nt, nph, a))
+    assert np.max(np.abs(back - a)) < 1e-13 * np.max(np.abs(a))
+
+
+# ------------------------------------------------- model on one shell
+
+def one_shell_problem(orc, L, ntheta=None, nphi=None, mean=0):
+    """N = 1, F = 1, w = r = 1, alpha = beta = 1: a_lin = n, a_nl = Phi_NL(n)."""
+    one = np.ones(1)
+    return orc.Problem(L, one, one, np.ones((L + 1, 1, 1)), np.ones((L + 1, 1)),
+                       np.ones((L + 1, 1)), ntheta=ntheta, nphi=nphi, mean_mode=mean)
+
+
+@pytest.mark.parametrize("L", [2, 5, 8])
+def test_phi_nl_matches_gaunt_bruteforce(orc, L):
+    rng = np.random.default_rng(10 + L)
+    a = rand_alm(L, rng)
+    P = one_shell_problem(orc, L)
+    out = P.forward(a[None, :], 0.0, want_phi=True)
+    ref = np.array(gaunt.phi_nl_sample(a, L))
+    got = out["phiNL"][0]
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(ref))
+    # a_nl of this trivial radial problem is Phi_NL itself
+    assert np.max(np.abs(out["aT_nl"] - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_phi_nl_gaunt_on_paper_grid_shape(orc):
+    """The grid size rule ntheta = ceil((3L+1)/2), nphi = 3L+1 is what makes
+    the brute-force equality exact; one ring fewer breaks it."""
+    L = 6
+    a = rand_alm(L, np.random.default_rng(3))
+    ref = np.array(gaunt.phi_nl_sample(a, L))
+    good = one_shell_problem(orc, L).forward(a[None], 0.0)["aT_nl"]
+    assert np.max(np.abs(good - ref)) < 1e-12 * np.max(np.abs(ref))
+    bad = one_shell_problem(orc, L, ntheta=inputs.min_ntheta(L) - 1).forward(a[None], 0.0)["aT_nl"]
+    assert np.max(np.abs(bad - ref)) > 1e-6 * np.max(np.abs(ref))
+
+
+def test_alias_at_three_l_only_hits_l_eq_m_eq_L(orc):
+    L = 6
+    a = rand_alm(L, np.random.default_rng(4))
+    exact = one_shell_problem(orc, L, nphi=3 * L + 1).forward(a[None], 0.0)["aT_nl"]
+    short = one_shell_problem(orc, L, nphi=3 * L).forward(a[None], 0.0)["aT_nl"]
+    diff = np.abs(short - exact)
+    assert diff[idx(L, L)] > 1e-3 * np.max(np.abs(exact))
+    diff[idx(L, L)] = 0
+    assert np.max(diff) < 1e-12 * np.max(np.abs(exact))
+    # the missing term is the square of the l = m = L mode folded back:
+    # 2 pi conj(G_L)^2 summed over rings with the analysis weights
+    x, wq = orc.gl_grid(inputs.min_ntheta(L))
+    GL = np.array([special.sph_harm_y(L, L, math.acos(xi), 0.0).real * a[idx(L, L)] for xi in x])
+    lamLL = np.array([special.sph_harm_y(L, L, math.acos(xi), 0.0).real for xi in x])
+    alias = np.sum(wq * lamLL * 2 * math.pi * np.conj(GL) ** 2)
+    assert abs((short - exact)[idx(L, L)] - alias) < 1e-12 * abs(alias)
+
+
+def test_closed_form_single_dipole(orc):
+    """Phi = c Y_10: Phi^2 = c^2 (3/4pi) cos^2 theta, so [Phi^2]_00 = c^2/sqrt(4 pi)
+    (removed by the mean) and [Phi^2]_20 = c^2/sqrt(5 pi); nothing else."""
+    L, c = 4, 1.7
+    a = np.zeros(nlm(L), dtype=complex)
+    a[idx(1, 0)] = c
+    out = one_shell_problem(orc, L).forward(a[None], 0.0, want_mu=True)
+    nl = out["aT_nl"]
+    ref = np.zeros_like(nl)
+    ref[idx(2, 0)] = c * c / math.sqrt(5 * math.pi)
+    assert np.max(np.abs(nl - ref)) < 1e-14
+    # the removed mean is the sky average of Phi^2 = c^2/(4 pi)
+    assert abs(out["mu"][0] - c * c / (4 * math.pi)) < 1e-15
+
+
+def test_closed_form_monopole_has_no_nonlinear_part(orc):
+    L = 5
+    a = np.zeros(nlm(L), dtype=complex)
+    a[0] = 0.8
+    nl = one_shell_problem(orc, L).forward(a[None], 0.0)["aT_nl"]
+    assert np.max(np.abs(nl)) < 1e-15
+
+
+def test_sample_mean_is_parseval(orc):
+    L = 20
+    a = rand_alm(L, np.random.default_rng(5))
+    mu = one_shell_problem(orc, L).forward(a[None], 0.0, want_mu=True)["mu"][0]
+    ls, ms = inputs.lm_arrays(L)
+    ref = np.sum(np.where(ms == 0, 1.0, 2.0) * np.abs(a) ** 2) / (4 * math.pi)
+    assert abs(mu - ref) < 1e-13 * ref
+
+
+# -------------------------------------------- multi-shell properties
+
+@pytest.fixture(scope="module")
+def tiny(orc):
+    cfg = inputs.CONFIGS["tiny"]
+    L, N = cfg["lmax"], cfg["nshell"]
+    p = inputs.problem(L, N)
+    P = orc.Problem(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"])
+    n = inputs.noise(L, N, inputs.realization_seed(0))
+    return P, p, n
+
+
+def test_fnl_zero_and_linearity(orc, tiny):
+    P, p, n = tiny
+    o0 = P.forward(n, 0.0)
+    o1 = P.forward(n, 100.0)
+    for X in "TE":
+        assert np.array_equal(o0["a" + X], o0["a" + X + "_lin"])
+        scale = np.max(np.abs(o1["a" + X + "_nl"])) * 100
+        assert np.max(np.abs(o1["a" + X] - o0["a" + X] - 100 * o1["a" + X + "_nl"])) < 1e-13 * scale
+
+
+def test_nonlinear_part_is_quadratic_in_noise(orc, tiny):
+    P, p, n = tiny
+    a1 = P.forward(n, 0.0)["aT_nl"]
+    a3 = P.forward(3.0 * n, 0.0)["aT_nl"]
+    assert np.max(np.abs(a3 - 9 * a1)) < 1e-13 * np.max(np.abs(a3))
+    l1 = P.forward(n, 0.0)["aT_lin"]
+    l3 = P.forward(3.0 * n, 0.0)["aT_lin"]
+    assert np.max(np.abs(l3 - 3 * l1)) < 1e-13 * np.max(np.abs(l3))
+
+
+def test_ensemble_mean_changes_only_l0(orc, tiny):
+    P, p, n = tiny
+    Pe = orc.Problem(P.lmax, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                     mean_mode=orc.MEAN_ENSEMBLE)
+    s = P.forward(n, 0.0, want_mu=True)
+    e = Pe.forward(n, 0.0, want_mu=True)
+    d = np.abs(s["aT_nl"] - e["aT_nl"])
+    assert d[0] > 0
+    d[0] = 0
+    assert np.max(d) < 1e-13 * np.max(np.abs(s["aT_nl"]))
+    # ensemble variance sum_l (2l+1)/(4 pi) sum_j F_ij^2 equals the covariance form
+    ell = np.arange(P.lmax + 1)
+    ref = np.einsum("l,lii->i", (2 * ell + 1) / (4 * math.pi), p["cov"])
+    assert np.max(np.abs(e["mu"] / ref - 1)) < 1e-9
+
+
+def test_radial_sum_is_the_line_of_sight_integral(orc):
+    """F = I and n_j = g(r_j) for a smooth g: a_lm = sum_i w_i r_i^2 alpha(r_i) g(r_i)
+    must approach int dr r^2 alpha(r) g(r) (Eq. phi2alm_r) at the trapezoid rate."""
+    L = 2
+    g = lambda r: np.cos((r - 13000.0) / 700.0) * 1e-4
+    alpha = lambda r: np.exp(-((r - 14000.0) ** 2) / (2 * 150.0 ** 2))
+    exact, _ = integrate.quad(lambda r: r * r * alpha(r) * g(r), 13000, 15000, epsabs=0, epsrel=1e-13,
+                              limit=200)
+    errs = []
+    for N in (41, 81, 161):
+        r, w = inputs.radial_nodes(N)
+        F = np.broadcast_to(np.eye(N), (L + 1, N, N)).copy()
+        al = np.broadcast_to(alpha(r), (L + 1, N)).copy()
+        P = orc.Problem(L, r, w, F, al, al)
+        n = np.zeros((N, nlm(L)), dtype=complex)
+        n[:, idx(1, 1)] = g(r)
+        a = P.forward(n, 0.0)["aT_lin"][idx(1, 1)]
+        errs.append(abs(a - exact))
+        # trapezoid error bound (b-a) h^2/12 max|f''|
+        h = 2000.0 / (N - 1)
+        rr = np.linspace(13000, 15000, 20001)
+        f = rr * rr * alpha(rr) * g(rr)
+        f2 = np.max(np.abs(np.gradient(np.gradient(f, rr), rr)))
+        assert abs(a - exact) <= 2000.0 * h * h / 12 * f2 * 1.05
+    # second-order convergence
+    assert errs[1] / errs[2] > 3.5 and errs[0] / errs[1] > 3.5
+
+
+def test_linear_spectrum_identity(orc):
+    """At f_NL = 0, E|a^X_lm|^2 = sum_ij W_i C_l(r_i,r_j) W_j with the covariance
+    of Eq. cov_phi: chi^2 over l of (2l+1) Chat_l / C_l on many realizations."""
+    from scipy import stats
+    L, N = 32, 16
+    p = inputs.problem(L, N)
+    P = orc.Problem(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"])
+    base = p["w"] * p["r"] ** 2
+    WT = p["alpha"] * base
+    WE = p["beta"] * base
+    CTT = np.einsum("li,lij,lj->l", WT, p["cov"], WT)
+    CEE = np.einsum("li,lij,lj->l", WE, p["cov"], WE)
+    ls, ms = inputs.lm_arrays(L)
+    c = np.where(ms == 0, 1.0, 2.0)
+    chiT = chiE = 0.0
+    dofT = dofE = 0
+    nreal = 24
+    for rr in range(nreal):
+        n = inputs.noise(L, N, 5000 + rr)
+        o = P.forward(n, 0.0)
+        pT = np.bincount(ls, weights=c * np.abs(o["aT_lin"]) ** 2)
+        pE = np.bincount(ls, weights=c * np.abs(o["aE_lin"]) ** 2)
+        chiT += np.sum(pT / CTT)
+        dofT += np.sum(2 * np.arange(L + 1) + 1)
+        chiE += np.sum(pE[2:] / CEE[2:])
+        dofE += np.sum(2 * np.arange(2, L + 1) + 1)
+    for chi, dof in ((chiT, dofT), (chiE, dofE)):
+        pval = 2 * min(stats.chi2.cdf(chi, dof), stats.chi2.sf(chi, dof))
+        assert pval > 1e-3, (chi, dof)
