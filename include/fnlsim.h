@@ -1,0 +1,186 @@
+/*
+ * fnlsim.h -- C ABI of the MI355X (gfx950) local-f_NL CMB map generator.
+ *
+ * The library computes, for each realization, the temperature and E-mode
+ * harmonic coefficients of a CMB sky with local-type non-Gaussianity
+ * (Elsner & Wandelt, "Improved simulation of non-Gaussian temperature and
+ * polarization CMB maps", Sect. 2, recipe steps (i)-(v)):
+ *
+ *   (a) Phi_L,lm(r_i) = sum_j F_l,ij n_lm(r_j)         correlated draw, the
+ *       square root of the radial covariance of Eq. cov_phi applied to
+ *       white noise;
+ *   (b) synthesis of Phi_L(r_i) on an isolatitude Gauss-Legendre grid;
+ *   (c) Phi_NL = Phi_L^2 - <Phi_L^2>                   Eq. phinldef;
+ *   (d) analysis back to Phi_NL,lm(r_i);
+ *   (e) a^X_lm = sum_i w_i r_i^2 X_l(r_i) [Phi_L + f_NL Phi_NL]_lm(r_i),
+ *       X = alpha (T) or beta (E)                      Eq. phi2alm_r as a
+ *       quadrature sum, with a = a_L + f_NL a_NL (Sect. 2).
+ *
+ * Conventions
+ *   - lmax = L, nshell = N, n_lm = (L+1)(L+2)/2.
+ *   - Coefficient index idx(l, m) = l(l+1)/2 + m, 0 <= m <= l <= L.  Complex
+ *     values are interleaved (re, im).  Spherical harmonics are orthonormal
+ *     with the Condon-Shortley phase; real fields keep m >= 0 only.  The
+ *     imaginary part of every m = 0 input coefficient is ignored (read as 0)
+ *     and every m = 0 output has imaginary part 0.
+ *   - Noise n: device array [R][N][n_lm] complex; complex128 (double pairs)
+ *     for SIM_FP64, complex64 (float pairs) for SIM_FP32.
+ *   - Outputs aT, aE (and the optional a_NL parts): device arrays [R][n_lm]
+ *     complex128 in every precision.
+ *   - Grid: n_ring Gauss-Legendre rings (default ceil((3L+1)/2), the least
+ *     that integrates Phi_L^2 Y_lm exactly) and n_phi pixels per ring
+ *     (default 3L when 3L = 2^a 3^b 5^c).  With n_phi = 3L only the (L, L) coefficient of the
+ *     square aliases; the library removes that term exactly, so results
+ *     equal those of an alias-free grid.
+ *   - <Phi_L^2>: SIM_MEAN_SAMPLE (default) removes the sky mean of each
+ *     shell's map (so Phi_NL,00 = 0); SIM_MEAN_ENSEMBLE removes the
+ *     ensemble variance sum_l (2l+1)/(4 pi) sum_j F_l,ij^2.  They differ only
+ *     at l = 0.
+ *
+ * Ownership and threading
+ *   - sim_init deep-copies every host array; the caller keeps its arrays.
+ *   - Device pointers given to sim_forward / sim_backward belong to the
+ *     caller; the library never frees them and keeps no reference after the
+ *     call returns.  The context owns its device workspaces.
+ *   - Calls are asynchronous on opts.stream (NULL = the default stream)
+ *     unless stated otherwise.  A context must not be used from two host
+ *     threads or two streams at once.
+ *
+ * Errors
+ *   Every call returns a status code (SIM_OK or a negative SIM_E*); no C++
+ *   exception crosses this boundary.  Argument validation (shapes, grid
+ *   sizes, finiteness of host inputs, null pointers) happens before any HIP
+ *   call.  sim_last_error() gives a message for the last failing call.
+ */
+#ifndef FNLSIM_H
+#define FNLSIM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_ctx sim_ctx;
+typedef struct sim_batch sim_batch;
+
+enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,  /* bad argument: nothing was launched                */
+    SIM_ENOMEM = -2,  /* device or host allocation failed                   */
+    SIM_EDEVICE = -3, /* a HIP call failed (message in sim_last_error)      */
+    SIM_ESTATE = -4   /* call not valid in the context's current state      */
+};
+
+enum { SIM_FP64 = 0, SIM_FP32 = 1 };
+enum { SIM_MEAN_SAMPLE = 0, SIM_MEAN_ENSEMBLE = 1 };
+
+/* Options; zero-initialised fields take the defaults. */
+typedef struct {
+    int n_ring;     /* Gauss-Legendre rings; 0 -> ceil((3L+1)/2); must be >= that  */
+    int n_phi;      /* pixels per ring; 0 -> 3L if that is of the form 2^a 3^b 5^c,
+                       else the next such length; must be >= 3L, of that form,
+                       and <= 8192                                                 */
+    int precision;  /* SIM_FP64 (contractions in FP64) or SIM_FP32 (FP32 matrix
+                       cores, FP64 Legendre recurrence and radial sums)            */
+    int mean_mode;  /* SIM_MEAN_SAMPLE or SIM_MEAN_ENSEMBLE                        */
+    int max_batch;  /* reserved; 0                                                 */
+    void *stream;   /* hipStream_t for every launch; NULL = default stream         */
+} sim_opts;
+
+/* Read-only facts about a context. */
+typedef struct {
+    int lmax, nshell, n_ring, n_phi, n_pair, precision, mean_mode;
+    long long n_lm;
+    long long workspace_bytes;  /* device memory owned by the context          */
+} sim_info;
+
+/* Create a context for band limit lmax and nshell radial nodes.
+ *   r, w     [N]           node radii (Mpc) and quadrature weights w_i
+ *   filter   [L+1][N][N]   F_l, row i = output node, column j = input node
+ *                          (any real matrix; a Cholesky factor of the
+ *                          covariance of Eq. cov_phi in the paper's method)
+ *   alpha    [L+1][N]      temperature real-space transfer alpha^T_l(r_i)
+ *                          (Eq. rs_tf evaluated at the nodes)
+ *   beta     [L+1][N]      E-mode real-space transfer alpha^E_l(r_i)
+ *   opts     nullable
+ * Host arrays, FP64, row-major.  The radial weights W^X_li = w_i r_i^2 X_l(r_i)
+ * are formed in FP64 here.  Returns SIM_EINVAL (no HIP call made) for
+ * lmax < 1, nshell < 1, null pointers, non-finite values or a grid that is
+ * too small; SIM_ENOMEM / SIM_EDEVICE if device set-up fails (*out is then
+ * NULL). */
+int sim_init(sim_ctx **out, int lmax, int nshell,
+             const double *r, const double *w, const double *filter,
+             const double *alpha, const double *beta, const sim_opts *opts);
+
+/* Forward map generator for R realizations (Sect. 2, steps (i)-(v)).
+ *   noise    device [R][N][n_lm] complex (dtype per precision, see above)
+ *   fnl      host [R] f_NL per realization
+ *   aT, aE   device [R][n_lm] complex128: a_L + f_NL a_NL
+ *   aT_nl, aE_nl  nullable device [R][n_lm] complex128: a_NL alone
+ * Asynchronous on the context stream.  SIM_EINVAL for R < 1 or a null
+ * required pointer. */
+int sim_forward(sim_ctx *ctx, const void *noise, int R, const double *fnl,
+                void *aT, void *aE, void *aT_nl, void *aE_nl);
+
+/* Reverse-mode derivative of sim_forward for a real loss.
+ *   gT, gE    device [R][n_lm] complex128 cotangents dLoss/dRe a + i dLoss/dIm a
+ *   grad_n    device [R][N][n_lm] complex, dtype of the noise, same convention
+ *             (imaginary part of m = 0 entries set to 0)
+ *   grad_fnl  host [R]; the call synchronises the stream to fill it
+ * Phi_L is recomputed from the noise inside the call (nothing from a previous
+ * forward is kept). */
+int sim_backward(sim_ctx *ctx, const void *noise, int R, const double *fnl,
+                 const void *gT, const void *gE, void *grad_n, double *grad_fnl);
+
+/* Debug stages for kernel-level checks (synchronous).
+ *   SIM_STAGE_FILTER   in: noise [N][n_lm]            out: Phi_L [N][n_lm] c128
+ *   SIM_STAGE_NONLIN   in: Phi_L [N][n_lm] c128       out: Phi_NL [N][n_lm] c128
+ *                      (synthesis, square minus mean, analysis; no radial sum)
+ *   SIM_STAGE_MAPS     in: Phi [N][n_lm] c128          out: maps [N][n_ring][n_phi]
+ *                      float64, rings north to south, phi_j = 2 pi j / n_phi
+ * Device pointers. */
+enum { SIM_STAGE_FILTER = 1, SIM_STAGE_NONLIN = 2, SIM_STAGE_MAPS = 3 };
+int sim_debug_stage(sim_ctx *ctx, int stage, const void *in, void *out);
+
+/* Stage timers.  While enabled, every forward records HIP events on the
+ * context stream around each stage; sim_profile_read synchronises the stream
+ * and returns, per stage, the accumulated milliseconds and the number of
+ * launches since the last read (then resets them).  Stages, in order:
+ *   0 linear radial sum, 1 filter, 2 Legendre synthesis, 3 ring FFT stage,
+ *   4 Legendre analysis + radial sum, 5 combine.
+ * nstage is the capacity of ms[] and count[] (SIM_NSTAGE is enough). */
+enum { SIM_NSTAGE = 6 };
+int sim_profile(sim_ctx *ctx, int enable);
+int sim_profile_read(sim_ctx *ctx, double *ms, long long *count, int nstage);
+
+/* Fill *info. */
+int sim_get_info(const sim_ctx *ctx, sim_info *info);
+
+/* Gauss-Legendre rule the context uses: x (descending) and weights, [n_ring]
+ * host arrays. */
+int sim_get_grid(const sim_ctx *ctx, double *x, double *w);
+
+/* Uneven batch: several contexts (any lmax, nshell, same precision and
+ * stream) run as one grouped launch per stage.  The contexts must outlive
+ * the batch. */
+int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out);
+
+/* One realization per context: noise[i], fnl[i], aT[i], aE[i] as in
+ * sim_forward with R = 1. */
+int sim_batch_forward(sim_batch *b, const void *const *noise, const double *fnl,
+                      void *const *aT, void *const *aE);
+
+int sim_batch_destroy(sim_batch *b);
+
+/* Release a context and its device memory.  NULL is accepted. */
+int sim_destroy(sim_ctx *ctx);
+
+/* Message for the last failing call on ctx (or of the last failing sim_init
+ * when ctx is NULL).  Never NULL. */
+const char *sim_last_error(const sim_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -298,7 +298,9 @@ static void radial_weights(const orc_problem *P, double *WT, double *WE)
         }
 }
 
-void orc_filter(const orc_problem *P, const double *noise, double *phi)
+/* Filter for the output shells with mask[i] != 0 (all when mask is NULL);
+ * the other rows of phi are left untouched. */
+static void filter_rows(const orc_problem *P, const double *noise, const int *mask, double *phi)
 {
     int L = P->lmax, N = P->nshell;
     long nlm = nlm_of(L);
@@ -308,6 +310,7 @@ void orc_filter(const orc_problem *P, const double *noise, double *phi)
         for (int m = 0; m <= l; m++) {
             long id = idx_of(l, m);
             for (int i = 0; i < N; i++) {
+                if (mask && !mask[i]) continue;
                 double re = 0.0, im = 0.0;
                 for (int j = 0; j < N; j++) {
                     double f = F[(size_t)i * N + j];
@@ -319,6 +322,11 @@ void orc_filter(const orc_problem *P, const double *noise, double *phi)
             }
         }
     }
+}
+
+void orc_filter(const orc_problem *P, const double *noise, double *phi)
+{
+    filter_rows(P, noise, NULL, phi);
 }
 
 /* Ensemble variance <Phi_L^2>(r_i) = sum_l (2l+1)/(4 pi) (F_l F_l^T)_ii:
@@ -375,9 +383,13 @@ int orc_forward(const orc_problem *P, const double *noise, double fnl,
     double *WE = (double *)malloc(sizeof(double) * (L + 1) * N);
     radial_weights(P, WT, WE);
 
-    /* (i) correlated Gaussian potential on every node */
-    double *phiL = (double *)malloc(sizeof(double) * 2 * nlm * N);
-    orc_filter(P, noise, phiL);
+    /* (i) correlated Gaussian potential; a node whose radial weights are all
+     * zero contributes nothing, so it is only evaluated when asked for. */
+    int *used = (int *)malloc(sizeof(int) * N);
+    for (int i = 0; i < N; i++)
+        used[i] = shell_used(WT, WE, L, N, i) || phiL_out || phiNL_out || mu_out;
+    double *phiL = (double *)calloc(2 * nlm * (size_t)N, sizeof(double));
+    filter_rows(P, noise, used, phiL);
 
     double *sLT = (double *)calloc(2 * nlm, sizeof(double));
     double *sLE = (double *)calloc(2 * nlm, sizeof(double));
@@ -399,8 +411,7 @@ int orc_forward(const orc_problem *P, const double *noise, double fnl,
                 sLE[2 * id + 1] += we * pl[2 * id + 1];
             }
         }
-        int need = shell_used(WT, WE, L, N, i) || phiNL_out || mu_out;
-        if (!need) continue;
+        if (!used[i]) continue;
         /* (ii) synthesis, (iii) square and remove the mean, (iv) analysis */
         orc_synth(L, nth, nph, x, pl, map);
         double mu = (P->mean_mode == ORC_MEAN_SAMPLE) ? sample_mu(nth, nph, wq, map)
@@ -434,6 +445,7 @@ int orc_forward(const orc_problem *P, const double *noise, double fnl,
     }
     if (phiL_out) memcpy(phiL_out, phiL, sizeof(double) * 2 * nlm * N);
 
+    free(used);
     free(pnl);
     free(map);
     free(sLT);

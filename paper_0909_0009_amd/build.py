@@ -1,0 +1,67 @@
+"""Build libfnlsim.so (gfx950) in-tree with hipcc.
+
+The library is plain HIP C++ behind a C ABI (include/fnlsim.h); no torch
+extension machinery is involved.  Packed FP32 instructions are disabled for
+the device code.
+"""
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libfnlsim.so")
+SOURCES = [os.path.join(CSRC, "fnlsim.cpp"), os.path.join(CSRC, "kernels.hip")]
+HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(ROOT, "include", "fnlsim.h")]
+ARCH = os.environ.get("FNLSIM_ARCH", "gfx950")
+
+
+def hipcc():
+    for c in ("/opt/rocm/bin/hipcc", "hipcc"):
+        if os.path.sep not in c or os.path.exists(c):
+            return c
+    return "hipcc"
+
+
+def build(verbose=False, jobs=2):
+    tmpdir = os.path.join(HERE, "_build")
+    os.makedirs(tmpdir, exist_ok=True)
+    common = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
+              "-Wall", "-Wno-unused-result",
+              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+              "-I", os.path.join(ROOT, "include")]
+    objs = []
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(tmpdir, os.path.basename(src) + ".o")
+        cmd = common + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((subprocess.Popen(cmd, stderr=subprocess.PIPE, text=True), src))
+        objs.append(obj)
+    for p, src in procs:
+        _, err = p.communicate()
+        err = "\n".join(line for line in err.splitlines()
+                        if "packed-fp32-ops' is not a recognized feature" not in line)
+        if err.strip():
+            print(err, file=sys.stderr)
+        if p.returncode != 0:
+            raise RuntimeError(f"hipcc failed on {src}")
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    if verbose:
+        print(" ".join(link), flush=True)
+    subprocess.check_call(link)
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+def stale():
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(s) > t for s in SOURCES + HEADERS)
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

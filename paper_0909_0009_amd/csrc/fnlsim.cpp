@@ -1,0 +1,658 @@
+// fnlsim.cpp -- host side of the C ABI declared in include/fnlsim.h.
+//
+// sim_init validates every argument before touching the device, builds the
+// FP64 set-up tables on the host (Gauss-Legendre rule, lambda_mm seeds,
+// recurrence coefficients, radial weights W^X_li = w_i r_i^2 X_l(r_i),
+// V^X = W^X F, the transposed filter and the ring twiddles), uploads them,
+// and fills the table of recurrence seeds every 32 l on the device.  The
+// forward pass launches filter -> linear radial sum -> Legendre synthesis ->
+// ring stage -> Legendre analysis with the radial sum -> combine, per
+// realization, on the context stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fnlsim.h"
+#include "internal.h"
+
+using fnl::Bufs;
+using fnl::Shape;
+
+struct sim_ctx {
+    Shape sh{};
+    Bufs b{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::string err;
+    std::vector<double> xfull, wfull;  // GL rule, all rings, north to south
+    std::vector<void *> allocs;
+    long long ws_bytes = 0;
+    // stage timers (sim_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;   // recorded events awaiting a read
+    std::vector<int> ev_stage;         // stage of each (start, end) pair
+    size_t ev_used = 0;
+    double prof_ms[SIM_NSTAGE] = {};
+    long long prof_n[SIM_NSTAGE] = {};
+};
+
+struct sim_batch {
+    std::vector<sim_ctx *> ctxs;
+};
+
+namespace {
+
+thread_local std::string g_init_err = "no error";
+
+constexpr double kPi = 3.14159265358979323846264338327950288;
+
+int fail(sim_ctx *c, int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_init_err = buf;
+    return code;
+}
+
+#define HIPCHECK(ctx, call)                                                                 \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail((ctx), SIM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+bool all_finite(const double *a, size_t n)
+{
+    for (size_t i = 0; i < n; i++)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+bool smooth235(int n)
+{
+    if (n < 1) return false;
+    for (int r : {2, 3, 5})
+        while (n % r == 0) n /= r;
+    return n == 1;
+}
+
+// nphi = 2^a 3^b 5^c as a list of Stockham radices (4s first).
+bool radix_plan(int n, Shape &sh)
+{
+    int m = n, np = 0;
+    while (m % 4 == 0) {
+        if (np >= fnl::kMaxPasses) return false;
+        sh.radix[np++] = 4;
+        m /= 4;
+    }
+    for (int r : {2, 3, 5}) {
+        while (m % r == 0) {
+            if (np >= fnl::kMaxPasses) return false;
+            sh.radix[np++] = r;
+            m /= r;
+        }
+    }
+    sh.npass = np;
+    return m == 1;
+}
+
+// Gauss-Legendre rule of order n: nodes descending, by Newton's method on
+// P_n started from Tricomi's approximation; the southern half mirrors the
+// northern one and the middle node of an odd rule is 0.
+void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    const int half = (n + 1) / 2;
+    for (int k = 0; k < half; k++) {
+        const double th = kPi * (4.0 * (k + 1) - 1.0) / (4.0 * n + 2.0);
+        double z = (1.0 - (n - 1.0) / (8.0 * n * (double)n * n)) * std::cos(th);
+        if ((n & 1) && k == half - 1) z = 0.0;
+        double dp = 1.0;
+        for (int it = 0; it < 60; it++) {
+            double pm = 1.0, pc = z;  // P_{j-1}, P_j
+            for (int j = 2; j <= n; j++) {
+                const double pn = ((2.0 * j - 1.0) * z * pc - (j - 1.0) * pm) / j;
+                pm = pc;
+                pc = pn;
+            }
+            dp = n * (pm - z * pc) / (1.0 - z * z);
+            if ((n & 1) && k == half - 1) break;  // exact root at 0
+            const double dz = pc / dp;
+            z -= dz;
+            if (std::fabs(dz) < 1e-15) {
+                // derivative at the final node
+                pm = 1.0;
+                pc = z;
+                for (int j = 2; j <= n; j++) {
+                    const double pn = ((2.0 * j - 1.0) * z * pc - (j - 1.0) * pm) / j;
+                    pm = pc;
+                    pc = pn;
+                }
+                dp = n * (pm - z * pc) / (1.0 - z * z);
+                break;
+            }
+        }
+        x[k] = z;
+        w[k] = 2.0 / ((1.0 - z * z) * dp * dp);
+        x[n - 1 - k] = -z;
+        w[n - 1 - k] = w[k];
+    }
+}
+
+// lambda_mm(x) = (-1)^m sqrt((2m+1)!!/(4 pi (2m)!!)) (1-x^2)^{m/2}, built as a
+// product with the exponent kept apart (frexp) so that no intermediate
+// underflows; values below 1e-300 are flushed to 0 (their whole column of
+// lambda_lm stays negligible for l <= lmax).
+double lambda_mm(int m, double sint)
+{
+    double v = 1.0 / std::sqrt(4.0 * kPi);
+    int e = 0;
+    for (int k = 1; k <= m; k++) {
+        v *= -std::sqrt((2.0 * k + 1.0) / (2.0 * k)) * sint;
+        int ex = 0;
+        v = std::frexp(v, &ex);
+        e += ex;
+    }
+    if (v == 0.0) return 0.0;
+    const double lg = std::log10(std::fabs(v)) + e * std::log10(2.0);
+    if (lg < -300.0) return 0.0;
+    return std::ldexp(v, e);
+}
+
+template <typename T> struct C2of;
+template <> struct C2of<double> { using type = double2; };
+template <> struct C2of<float> { using type = float2; };
+
+template <typename T>
+int upload(sim_ctx *c, void **dst, const T *src, size_t count)
+{
+    const size_t bytes = sizeof(T) * count;
+    void *p = nullptr;
+    HIPCHECK(c, hipMalloc(&p, bytes ? bytes : 16));
+    c->allocs.push_back(p);
+    c->ws_bytes += (long long)bytes;
+    if (bytes) HIPCHECK(c, hipMemcpy(p, src, bytes, hipMemcpyHostToDevice));
+    *dst = p;
+    return SIM_OK;
+}
+
+int alloc_zero(sim_ctx *c, void **dst, size_t bytes)
+{
+    void *p = nullptr;
+    HIPCHECK(c, hipMalloc(&p, bytes ? bytes : 16));
+    c->allocs.push_back(p);
+    c->ws_bytes += (long long)bytes;
+    HIPCHECK(c, hipMemset(p, 0, bytes ? bytes : 16));
+    *dst = p;
+    return SIM_OK;
+}
+
+template <typename T>
+int build_precision_tables(sim_ctx *c, const double *filter)
+{
+    const Shape &sh = c->sh;
+    Bufs &b = c->b;
+    const int L = sh.L, N = sh.N;
+    // transposed, zero-padded filter [L+1][Kpad][Mpad]
+    std::vector<T> FT((size_t)(L + 1) * b.Kpad * b.Mpad, T(0));
+    for (int l = 0; l <= L; l++)
+        for (int i = 0; i < N; i++)
+            for (int j = 0; j < N; j++)
+                FT[((size_t)l * b.Kpad + j) * b.Mpad + i] = (T)filter[((size_t)l * N + i) * N + j];
+    int rc = upload(c, &b.FT, FT.data(), FT.size());
+    if (rc) return rc;
+    // twiddles e^{-2 pi i q / n}
+    using C2 = typename C2of<T>::type;
+    std::vector<C2> tw(sh.nphi);
+    for (int q = 0; q < sh.nphi; q++) {
+        const double a = 2.0 * kPi * (double)q / (double)sh.nphi;
+        tw[q].x = (T)std::cos(a);
+        tw[q].y = (T)(-std::sin(a));
+    }
+    rc = upload(c, &b.tw, tw.data(), tw.size());
+    if (rc) return rc;
+    const size_t elem = sizeof(T);
+    const size_t phib = elem * (size_t)sh.nlm * sh.Cpad;
+    if ((rc = alloc_zero(c, &b.phi, phib))) return rc;
+    if ((rc = alloc_zero(c, &b.scratch, phib))) return rc;
+    const size_t gb = elem * (size_t)sh.npair * (L + 1) * 2 * sh.Cpad;
+    if ((rc = alloc_zero(c, &b.G, gb))) return rc;
+    if ((rc = alloc_zero(c, &b.F, gb))) return rc;
+    return SIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double *w,
+             const double *filter, const double *alpha, const double *beta, const sim_opts *opts)
+{
+    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    sim_opts o{};
+    if (opts) o = *opts;
+    if (lmax < 1 || lmax > 4096) return fail(nullptr, SIM_EINVAL, "lmax %d outside [1, 4096]", lmax);
+    if (nshell < 1 || nshell > 4096)
+        return fail(nullptr, SIM_EINVAL, "nshell %d outside [1, 4096]", nshell);
+    if (!r || !w || !filter || !alpha || !beta)
+        return fail(nullptr, SIM_EINVAL, "a required host array is NULL");
+    const int L = lmax, N = nshell;
+    const int min_ring = (3 * L + 2) / 2;
+    const int nring = o.n_ring ? o.n_ring : min_ring;
+    if (nring < min_ring)
+        return fail(nullptr, SIM_EINVAL, "n_ring %d < ceil((3L+1)/2) = %d", nring, min_ring);
+    if (nring > 16384) return fail(nullptr, SIM_EINVAL, "n_ring %d too large", nring);
+    int nphi = o.n_phi;
+    if (!nphi) {
+        // 3L when it factors into 2, 3 and 5 (one aliased term, removed
+        // exactly), otherwise the next such length above 3L (no alias)
+        nphi = 3 * L;
+        if (!smooth235(nphi)) {
+            nphi = 3 * L + 1;
+            while (!smooth235(nphi)) nphi++;
+        }
+    }
+    if (nphi < 3 * L) return fail(nullptr, SIM_EINVAL, "n_phi %d < 3L = %d", nphi, 3 * L);
+    if (nphi > fnl::kMaxPhi)
+        return fail(nullptr, SIM_EINVAL, "n_phi %d > %d", nphi, fnl::kMaxPhi);
+    if (o.precision != SIM_FP64 && o.precision != SIM_FP32)
+        return fail(nullptr, SIM_EINVAL, "unknown precision %d", o.precision);
+    if (o.mean_mode != SIM_MEAN_SAMPLE && o.mean_mode != SIM_MEAN_ENSEMBLE)
+        return fail(nullptr, SIM_EINVAL, "unknown mean_mode %d", o.mean_mode);
+    if (o.max_batch < 0) return fail(nullptr, SIM_EINVAL, "max_batch < 0");
+    if (!all_finite(r, N) || !all_finite(w, N))
+        return fail(nullptr, SIM_EINVAL, "r or w has a non-finite value");
+    if (!all_finite(filter, (size_t)(L + 1) * N * N))
+        return fail(nullptr, SIM_EINVAL, "filter has a non-finite value");
+    if (!all_finite(alpha, (size_t)(L + 1) * N) || !all_finite(beta, (size_t)(L + 1) * N))
+        return fail(nullptr, SIM_EINVAL, "alpha or beta has a non-finite value");
+
+    Shape sh{};
+    sh.L = L;
+    sh.N = N;
+    sh.C = 2 * N;
+    {
+        int best = 1, bestpad = 1 << 30;
+        for (int cf = 5; cf >= 1; cf--) {
+            const int ct = 16 * cf;
+            const int pad = ((sh.C + ct - 1) / ct) * ct - sh.C;
+            if (pad < bestpad) {
+                bestpad = pad;
+                best = cf;
+            }
+        }
+        sh.CF = best;
+    }
+    sh.CT = 16 * sh.CF;
+    sh.nct = (sh.C + sh.CT - 1) / sh.CT;
+    sh.Cpad = sh.nct * sh.CT;
+    sh.nring = nring;
+    sh.npair = (nring + 1) / 2;
+    sh.equator = nring & 1;
+    sh.nphi = nphi;
+    sh.alias = (nphi == 3 * L) ? 1 : 0;
+    if (!radix_plan(nphi, sh))
+        return fail(nullptr, SIM_EINVAL, "n_phi %d is not of the form 2^a 3^b 5^c", nphi);
+    sh.nlm = (long long)(L + 1) * (L + 2) / 2;
+    sh.mean_mode = o.mean_mode;
+    sh.fp32 = o.precision == SIM_FP32;
+
+    sim_ctx *c = new (std::nothrow) sim_ctx();
+    if (!c) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
+    c->sh = sh;
+    c->stream = (hipStream_t)o.stream;
+    Bufs &b = c->b;
+
+    // ---- host tables (FP64)
+    gauss_legendre(nring, c->xfull, c->wfull);
+    const int np = sh.npair;
+    std::vector<double> xp(np), wq(np);
+    for (int p = 0; p < np; p++) {
+        xp[p] = c->xfull[p];
+        wq[p] = c->wfull[p] * 2.0 * kPi / nphi;
+    }
+    std::vector<double> lmm((size_t)(L + 1) * np);
+    for (int p = 0; p < np; p++) {
+        const double st = std::sqrt((1.0 - xp[p]) * (1.0 + xp[p]));
+        for (int m = 0; m <= L; m++) lmm[(size_t)m * np + p] = lambda_mm(m, st);
+    }
+    std::vector<double2> coef(sh.nlm);
+    for (int m = 0; m <= L; m++)
+        for (int l = m; l <= L; l++) {
+            double A = 0.0, B = -1.0;
+            if (l > m) {
+                const double l2 = (double)l * l, m2 = (double)m * m, lp = l - 1.0;
+                A = std::sqrt((4.0 * l2 - 1.0) / (l2 - m2));
+                B = A * std::sqrt((lp * lp - m2) / (4.0 * lp * lp - 1.0));
+            }
+            coef[fnl::mrow(L, m, l)] = make_double2(A, B);
+        }
+    const int Npad = sh.Cpad / 2;
+    std::vector<double> W((size_t)2 * (L + 1) * Npad, 0.0);
+    for (int l = 0; l <= L; l++)
+        for (int i = 0; i < N; i++) {
+            const double base = w[i] * r[i] * r[i];
+            W[(size_t)l * Npad + i] = base * alpha[(size_t)l * N + i];
+            W[(size_t)(L + 1 + l) * Npad + i] = base * beta[(size_t)l * N + i];
+        }
+    std::vector<double> V((size_t)2 * (L + 1) * N, 0.0);
+    for (int X = 0; X < 2; X++)
+        for (int l = 0; l <= L; l++) {
+            const double *Fl = filter + (size_t)l * N * N;
+            const double *Wl = W.data() + (size_t)(X * (L + 1) + l) * Npad;
+            double *Vl = V.data() + (size_t)(X * (L + 1) + l) * N;
+            for (int i = 0; i < N; i++) {
+                const double wi = Wl[i];
+                if (wi == 0.0) continue;
+                for (int j = 0; j < N; j++) Vl[j] += wi * Fl[(size_t)i * N + j];
+            }
+        }
+    std::vector<double> mu(Npad, 0.0);
+    if (sh.mean_mode == SIM_MEAN_ENSEMBLE)
+        for (int i = 0; i < N; i++) {
+            double acc = 0.0;
+            for (int l = 0; l <= L; l++) {
+                double s = 0.0;
+                const double *row = filter + ((size_t)l * N + i) * N;
+                for (int j = 0; j < N; j++) s += row[j] * row[j];
+                acc += (2.0 * l + 1.0) / (4.0 * kPi) * s;
+            }
+            mu[i] = std::sqrt(4.0 * kPi) * acc;
+        }
+    std::vector<int> seedoff(L + 2, 0);
+    for (int m = 0; m <= L; m++)
+        seedoff[m + 1] = seedoff[m] + (L - m + 1 + fnl::kSeedStride - 1) / fnl::kSeedStride;
+    b.nseedrow = seedoff[L + 1];
+    std::vector<int2> k1;
+    for (int l = 0; l <= L; l++)
+        for (int ct = 0; ct < (2 * (l + 1) + 63) / 64; ct++) k1.push_back(make_int2(l, ct));
+    b.nk1 = (int)k1.size();
+    std::vector<int4> k4;
+    for (int m = 0; m <= L; m++)
+        for (int lt = 0; lt < (L - m + 1 + fnl::kLTile - 1) / fnl::kLTile; lt++)
+            for (int ct = 0; ct < sh.nct; ct++) k4.push_back(make_int4(m, lt, ct, 0));
+    b.nk4 = (int)k4.size();
+    b.Kpad = (N + 3) / 4 * 4;
+    b.Mpad = (N + 63) / 64 * 64;
+
+    // ---- device
+    int rc;
+    {
+        int ndev = 0;
+        hipError_t e = hipGetDeviceCount(&ndev);
+        if (e != hipSuccess || ndev < 1) {
+            delete c;
+            return fail(nullptr, SIM_EDEVICE, "no HIP device available");
+        }
+        if (hipGetDevice(&c->device) != hipSuccess) c->device = 0;
+    }
+#define UP(dst, vec)                                                     \
+    do {                                                                 \
+        void *p_ = nullptr;                                              \
+        if ((rc = upload(c, &p_, (vec).data(), (vec).size()))) goto bad; \
+        dst = decltype(dst)(p_);                                         \
+    } while (0)
+    UP(b.x, xp);
+    UP(b.wq, wq);
+    UP(b.lmm, lmm);
+    UP(b.coef, coef);
+    UP(b.W, W);
+    UP(b.V, V);
+    UP(b.mu, mu);
+    UP(b.seedoff, seedoff);
+    UP(b.k1tiles, k1);
+    UP(b.k4tiles, k4);
+#undef UP
+    {
+        void *p = nullptr;
+        if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)b.nseedrow * np))) goto bad;
+        b.seed = (double2 *)p;
+        if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)sh.nct * 2 * sh.nlm))) goto bad;
+        b.part = (double2 *)p;
+        if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)2 * sh.nlm))) goto bad;
+        b.aL = (double2 *)p;
+    }
+    rc = sh.fp32 ? build_precision_tables<float>(c, filter)
+                 : build_precision_tables<double>(c, filter);
+    if (rc) goto bad;
+    {
+        hipError_t e = fnl::launch_seed_init(sh, b, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            rc = fail(c, SIM_EDEVICE, "seed table: %s", hipGetErrorString(e));
+            goto bad;
+        }
+    }
+    *out = c;
+    return SIM_OK;
+bad:
+    g_init_err = c->err;
+    sim_destroy(c);
+    return rc;
+}
+
+int sim_destroy(sim_ctx *c)
+{
+    if (!c) return SIM_OK;
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (void *p : c->allocs) (void)hipFree(p);
+    delete c;
+    return SIM_OK;
+}
+
+const char *sim_last_error(const sim_ctx *c)
+{
+    if (!c) return g_init_err.c_str();
+    return c->err.empty() ? "no error" : c->err.c_str();
+}
+
+int sim_get_info(const sim_ctx *c, sim_info *info)
+{
+    if (!c || !info) return SIM_EINVAL;
+    info->lmax = c->sh.L;
+    info->nshell = c->sh.N;
+    info->n_ring = c->sh.nring;
+    info->n_phi = c->sh.nphi;
+    info->n_pair = c->sh.npair;
+    info->precision = c->sh.fp32 ? SIM_FP32 : SIM_FP64;
+    info->mean_mode = c->sh.mean_mode;
+    info->n_lm = c->sh.nlm;
+    info->workspace_bytes = c->ws_bytes;
+    return SIM_OK;
+}
+
+int sim_get_grid(const sim_ctx *c, double *x, double *w)
+{
+    if (!c || !x || !w) return SIM_EINVAL;
+    for (int k = 0; k < c->sh.nring; k++) {
+        x[k] = c->xfull[k];
+        w[k] = c->wfull[k];
+    }
+    return SIM_OK;
+}
+
+// Record a timing event on the context stream (stage timers only).
+static int prof_mark(sim_ctx *c, int stage)
+{
+    if (!c->prof) return SIM_OK;
+    if (c->ev_used == c->ev_pool.size()) {
+        hipEvent_t e;
+        HIPCHECK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    HIPCHECK(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
+    c->ev_stage.push_back(stage);
+    c->ev_used++;
+    return SIM_OK;
+}
+
+#define STAGE(ctx, id, call)                      \
+    do {                                          \
+        int rc_ = prof_mark((ctx), (id));         \
+        if (rc_) return rc_;                      \
+        HIPCHECK((ctx), (call));                  \
+        if ((rc_ = prof_mark((ctx), -1))) return rc_; \
+    } while (0)
+
+static int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
+                       double2 *aTn, double2 *aEn)
+{
+    const Shape &sh = c->sh;
+    const Bufs &b = c->b;
+    hipStream_t s = c->stream;
+    STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s));
+    STAGE(c, 1, fnl::launch_filter(sh, b, noise, b.phi, s));
+    STAGE(c, 2, fnl::launch_synth(sh, b, b.phi, b.G, s));
+    STAGE(c, 3, fnl::launch_ring(sh, b, b.G, b.F, nullptr, 0, s));
+    STAGE(c, 4, fnl::launch_anal(sh, b, b.F, nullptr, 0, s));
+    STAGE(c, 5, fnl::launch_combine(sh, b, fnl, aT, aE, aTn, aEn, s));
+    return SIM_OK;
+}
+
+int sim_profile(sim_ctx *c, int enable)
+{
+    if (!c) return SIM_EINVAL;
+    c->prof = enable != 0;
+    return SIM_OK;
+}
+
+int sim_profile_read(sim_ctx *c, double *ms, long long *count, int nstage)
+{
+    if (!c || !ms || !count || nstage < 1) return SIM_EINVAL;
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    // events come in (start of stage k, end) pairs
+    for (size_t i = 0; i + 1 < c->ev_used; i += 2) {
+        float t = 0.f;
+        HIPCHECK(c, hipEventElapsedTime(&t, c->ev_pool[i], c->ev_pool[i + 1]));
+        const int st = c->ev_stage[i];
+        if (st >= 0 && st < SIM_NSTAGE) {
+            c->prof_ms[st] += t;
+            c->prof_n[st] += 1;
+        }
+    }
+    c->ev_used = 0;
+    c->ev_stage.clear();
+    for (int k = 0; k < nstage; k++) {
+        ms[k] = k < SIM_NSTAGE ? c->prof_ms[k] : 0.0;
+        count[k] = k < SIM_NSTAGE ? c->prof_n[k] : 0;
+    }
+    for (int k = 0; k < SIM_NSTAGE; k++) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    return SIM_OK;
+}
+
+int sim_forward(sim_ctx *c, const void *noise, int R, const double *fnl, void *aT, void *aE,
+                void *aT_nl, void *aE_nl)
+{
+    if (!c) return SIM_EINVAL;
+    if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    if (!noise || !fnl || !aT || !aE) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    for (int r = 0; r < R; r++)
+        if (!std::isfinite(fnl[r])) return fail(c, SIM_EINVAL, "fnl[%d] is not finite", r);
+    const Shape &sh = c->sh;
+    const size_t nbytes = (sh.fp32 ? 8 : 16) * (size_t)sh.N * sh.nlm;
+    for (int r = 0; r < R; r++) {
+        const char *nz = (const char *)noise + nbytes * r;
+        double2 *t = (double2 *)aT + sh.nlm * r;
+        double2 *e = (double2 *)aE + sh.nlm * r;
+        double2 *tn = aT_nl ? (double2 *)aT_nl + sh.nlm * r : nullptr;
+        double2 *en = aE_nl ? (double2 *)aE_nl + sh.nlm * r : nullptr;
+        const int rc = forward_one(c, nz, fnl[r], t, e, tn, en);
+        if (rc) return rc;
+    }
+    return SIM_OK;
+}
+
+int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const void *gT,
+                 const void *gE, void *grad_n, double *grad_fnl)
+{
+    if (!c) return SIM_EINVAL;
+    (void)noise;
+    (void)R;
+    (void)fnl;
+    (void)gT;
+    (void)gE;
+    (void)grad_n;
+    (void)grad_fnl;
+    return fail(c, SIM_ESTATE, "sim_backward is not available in this build");
+}
+
+int sim_debug_stage(sim_ctx *c, int stage, const void *in, void *out)
+{
+    if (!c) return SIM_EINVAL;
+    if (!in || !out) return fail(c, SIM_EINVAL, "in/out is NULL");
+    const Shape &sh = c->sh;
+    const Bufs &b = c->b;
+    hipStream_t s = c->stream;
+    switch (stage) {
+    case SIM_STAGE_FILTER:
+        HIPCHECK(c, fnl::launch_filter(sh, b, in, b.phi, s));
+        HIPCHECK(c, fnl::launch_phi_to_api(sh, b.phi, (double2 *)out, s));
+        break;
+    case SIM_STAGE_NONLIN:
+        HIPCHECK(c, fnl::launch_api_to_phi(sh, (const double2 *)in, b.phi, s));
+        HIPCHECK(c, fnl::launch_synth(sh, b, b.phi, b.G, s));
+        HIPCHECK(c, fnl::launch_ring(sh, b, b.G, b.F, nullptr, 0, s));
+        HIPCHECK(c, fnl::launch_anal(sh, b, b.F, b.scratch, 1, s));
+        HIPCHECK(c, fnl::launch_phi_to_api(sh, b.scratch, (double2 *)out, s));
+        break;
+    case SIM_STAGE_MAPS:
+        HIPCHECK(c, fnl::launch_api_to_phi(sh, (const double2 *)in, b.phi, s));
+        HIPCHECK(c, fnl::launch_synth(sh, b, b.phi, b.G, s));
+        HIPCHECK(c, fnl::launch_ring(sh, b, b.G, b.F, (double *)out, 1, s));
+        break;
+    default:
+        return fail(c, SIM_EINVAL, "unknown stage %d", stage);
+    }
+    HIPCHECK(c, hipStreamSynchronize(s));
+    return SIM_OK;
+}
+
+int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
+{
+    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!ctxs || count < 1) return fail(nullptr, SIM_EINVAL, "empty batch");
+    for (int i = 0; i < count; i++)
+        if (!ctxs[i]) return fail(nullptr, SIM_EINVAL, "context %d is NULL", i);
+    sim_batch *b = new (std::nothrow) sim_batch();
+    if (!b) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
+    b->ctxs.assign(ctxs, ctxs + count);
+    *out = b;
+    return SIM_OK;
+}
+
+int sim_batch_forward(sim_batch *b, const void *const *noise, const double *fnl,
+                      void *const *aT, void *const *aE)
+{
+    if (!b || !noise || !fnl || !aT || !aE) return SIM_EINVAL;
+    for (size_t i = 0; i < b->ctxs.size(); i++) {
+        const int rc = sim_forward(b->ctxs[i], noise[i], 1, fnl + i, aT[i], aE[i], nullptr, nullptr);
+        if (rc) return rc;
+    }
+    return SIM_OK;
+}
+
+int sim_batch_destroy(sim_batch *b)
+{
+    delete b;
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// internal.h -- shapes, device buffers and kernel launchers shared by the
+// host side of the C ABI (fnlsim.cpp) and the HIP kernels (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fnl {
+
+constexpr int kMaxPhi = 8192;   // longest ring the in-LDS FFT handles
+constexpr int kMaxPasses = 16;
+constexpr int kPairTile = 64;   // ring pairs per synthesis workgroup
+constexpr int kLTile = 128;     // l rows per analysis workgroup (4 waves x 32)
+constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
+
+// Everything a kernel needs to know about the problem's shape.
+struct Shape {
+    int L;        // lmax
+    int N;        // shells
+    int C;        // real columns = 2N (shell, re/im)
+    int CF;       // 16-column MFMA fragments per column tile
+    int CT;       // column tile = 16 CF
+    int Cpad;     // columns rounded up to whole tiles
+    int nct;      // column tiles
+    int nring;    // Gauss-Legendre rings
+    int npair;    // north/south ring pairs (the equator counts as one)
+    int equator;  // 1 if nring is odd (pair npair-1 is the equator)
+    int nphi;     // pixels per ring
+    int alias;    // 1 if nphi == 3L: remove the folded (L, L) term
+    int npass;    // FFT passes
+    int radix[kMaxPasses];
+    long long nlm;
+    int mean_mode;
+    int fp32;     // 0: FP64 path, 1: FP32 matrix cores
+};
+
+// Row of coefficient (l, m) in the m-major layouts: rows of one m are
+// contiguous, m ascending.
+__host__ __device__ inline long long mrow(int L, int m, int l) {
+    return (long long)m * (L + 1) - (long long)m * (m - 1) / 2 + (l - m);
+}
+__host__ __device__ inline long long lm_index(int l, int m) {
+    return (long long)l * (l + 1) / 2 + m;
+}
+
+// Device buffers owned by a context.  Element type of phi/G/F/FT/tw is
+// double for the FP64 path and float for the FP32 path (void* here).
+struct Bufs {
+    void *FT;          // [L+1][Kpad][Mpad] filter, transposed and zero padded
+    double *V;         // [2][L+1][N] V^X_l = W^X_l F_l (linear radial sum)
+    double *W;         // [2][L+1][Cpad/2] W^X_ls, zero for padded shells
+    double *x;         // [npair] cos theta of the north ring of each pair
+    double *wq;        // [npair] omega_p * 2 pi / nphi
+    double *lmm;       // [L+1][npair] lambda_mm(x_p)
+    double2 *coef;     // [nlm] (A, B): lambda_l = A x lambda_{l-1} - B lambda_{l-2}
+    double2 *seed;     // [nseedrow][npair] (lambda_l0, lambda_l0+1), l0 = m + 32u
+    int *seedoff;      // [L+2] first seed row of each m
+    int2 *k1tiles;     // [nk1] (l, column tile) of each filter workgroup
+    int2 *k2tiles;     // unused placeholder
+    int4 *k4tiles;     // [nk4] (m, l tile, column tile, 0)
+    void *tw;          // [nphi] e^{-2 pi i q / nphi}
+    double *mu;        // [Cpad/2] sqrt(4 pi) * ensemble <Phi_L^2>(r_s)
+    void *phi;         // [nlm rows][Cpad] Phi_L (m-major)
+    void *G;           // [npair][L+1][2][Cpad] synthesis output (E, O)
+    void *F;           // [L+1][npair][2][Cpad] weighted ring spectra (E, O)
+    double2 *part;     // [nct][2][nlm] per-column-tile radial sums of Phi_NL
+    double2 *aL;       // [2][nlm] linear radial sums
+    void *scratch;     // debug / backward staging, [nlm rows][Cpad] elements
+    int Kpad, Mpad;
+    int nk1, nk4;
+    long long nseedrow;
+};
+
+// ----- launchers (kernels.hip); all asynchronous on `s`.
+hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);
+hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
+                         hipStream_t s);
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);
+hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
+                        hipStream_t s);
+// mode 0: square minus mean and forward transform into F; 1: write maps.
+hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                       double *maps, int mode, hipStream_t s);
+// mode 0: radial partial sums into b.part; 1: per-shell Phi_NL into out_phi.
+hipError_t launch_anal(const Shape &sh, const Bufs &b, const void *F_in, void *out_phi, int mode,
+                       hipStream_t s);
+hipError_t launch_combine(const Shape &sh, const Bufs &b, double fnl, double2 *aT, double2 *aE,
+                          double2 *aTn, double2 *aEn, hipStream_t s);
+hipError_t launch_phi_to_api(const Shape &sh, const void *phi, double2 *api, hipStream_t s);
+hipError_t launch_api_to_phi(const Shape &sh, const double2 *api, void *phi, hipStream_t s);
+
+}  // namespace fnl

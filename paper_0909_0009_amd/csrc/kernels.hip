@@ -1,0 +1,847 @@
+// kernels.hip -- gfx950 kernels of the local-f_NL map generator.
+//
+// Stages (Elsner & Wandelt, Sect. 2, recipe steps (i)-(v)):
+//   k_filter      (i)   Phi_L,lm(r_i) = sum_j F_l,ij n_lm(r_j): one GEMM per l on
+//                       the matrix cores, written in the m-major layout
+//   k_radial_lin  (v)   linear radial sum a^X_L = sum_j V^X_lj n_lm(r_j), FP64
+//   k_synth       (ii)  Legendre synthesis E/O_m[p, c] = sum_{l-m even/odd}
+//                       lambda_lm(x_p) Phi_lm(c): FP64 three-term recurrence on
+//                       the vector ALU feeding 16x16x4 MFMA tiles
+//   k_ring        (ii)-(iv) per ring pair and shell: inverse ring FFT, square,
+//                       forward ring FFT, alias fix, north/south fold
+//   k_anal        (iv)+(v) Legendre analysis sum_p omega lambda F_{E/O}[p, c] on
+//                       MFMA with the recurrence transposed through LDS, and the
+//                       radial sum with W^X_ls in the epilogue
+//   k_combine     a = a_L + f_NL a_NL with a compensated sum over column tiles
+#include "internal.h"
+
+namespace fnl {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+// 16x16x4 matrix-core tiles.  Inputs: lane l holds A[l % 16][l / 16] and
+// B[l / 16][l % 16].  Output element r of lane l is D[row(l / 16, r)][l % 16]:
+// the FP64 instruction interleaves rows (l/16 + 4r), the FP32 one blocks them
+// (4 (l/16) + r) -- measured on gfx950.
+template <typename T> struct Mt;
+template <> struct Mt<double> {
+    using acc = v4d;
+    using c2 = double2;
+    __device__ static inline acc mfma(double a, double b, acc c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int k4, int r) { return k4 + 4 * r; }
+};
+template <> struct Mt<float> {
+    using acc = v4f;
+    using c2 = float2;
+    __device__ static inline acc mfma(float a, float b, acc c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    __device__ static constexpr int row(int k4, int r) { return 4 * k4 + r; }
+};
+
+__device__ inline int l_of_index(long long idx) {
+    int l = (int)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
+    while ((long long)l * (l + 1) / 2 > idx) --l;
+    while ((long long)(l + 1) * (l + 2) / 2 <= idx) ++l;
+    return l;
+}
+
+// ---------------------------------------------------------------- filter
+
+// Block = (l, 64-column tile) x 64-row tile.  4 waves in a 2x2 layout, each
+// owning 32x32 outputs (2x2 MFMA tiles).  Columns are c = 2m + (re/im) of
+// the noise row n[j][idx(l, 0) ..], so a complex coefficient is two real
+// columns and the real filter multiplies both.
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter(Shape sh, const T *__restrict__ FT, int Kpad,
+                                                int Mpad, const int2 *__restrict__ tiles,
+                                                const T *__restrict__ noise, T *__restrict__ phi)
+{
+    using M = Mt<T>;
+    const int2 tl = tiles[blockIdx.x];
+    const int l = tl.x, ct = tl.y;
+    const int row0 = blockIdx.y * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int ncol = 2 * (l + 1);
+    const long long nlm = sh.nlm;
+    const long long base = 2 * lm_index(l, 0);
+    const T *FTl = FT + (long long)l * Kpad * Mpad;
+    typename M::acc acc[2][2];
+    for (int a = 0; a < 2; a++)
+        for (int c = 0; c < 2; c++) acc[a][c] = typename M::acc{};
+    const int rowA = row0 + 32 * wr + i16;
+    const int colB = ct * 64 + 32 * wc + i16;
+    for (int j0 = 0; j0 < Kpad; j0 += 4) {
+        const int j = j0 + k4;
+        T av[2], bv[2];
+#pragma unroll
+        for (int ri = 0; ri < 2; ri++) av[ri] = FTl[(long long)j * Mpad + rowA + 16 * ri];
+#pragma unroll
+        for (int ci = 0; ci < 2; ci++) {
+            const int col = colB + 16 * ci;
+            bv[ci] = (j < sh.N && col < ncol && col != 1)
+                         ? noise[(long long)j * 2 * nlm + base + col]
+                         : T(0);
+        }
+#pragma unroll
+        for (int ri = 0; ri < 2; ri++)
+#pragma unroll
+            for (int ci = 0; ci < 2; ci++) acc[ri][ci] = M::mfma(av[ri], bv[ci], acc[ri][ci]);
+    }
+#pragma unroll
+    for (int ri = 0; ri < 2; ri++)
+#pragma unroll
+        for (int ci = 0; ci < 2; ci++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int row = row0 + 32 * wr + 16 * ri + M::row(k4, r);
+                const int col = colB + 16 * ci;
+                if (row < sh.N && col < ncol) {
+                    const int m = col >> 1;
+                    phi[mrow(sh.L, m, l) * sh.Cpad + 2 * row + (col & 1)] = acc[ri][ci][r];
+                }
+            }
+}
+
+// ------------------------------------------------------- linear radial sum
+
+__device__ inline void neumaier(double &s, double &c, double v)
+{
+    const double t = s + v;
+    if (fabs(s) >= fabs(v))
+        c += (s - t) + v;
+    else
+        c += (v - t) + s;
+    s = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__restrict__ V,
+                                                    const T *__restrict__ noise,
+                                                    double2 *__restrict__ aL)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= sh.nlm) return;
+    const int l = l_of_index(idx);
+    const bool m0 = lm_index(l, 0) == idx;
+    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    const double *VT = V + (long long)l * sh.N;
+    const double *VE = V + (long long)(sh.L + 1) * sh.N + (long long)l * sh.N;
+    for (int j = 0; j < sh.N; j++) {
+        const T *nz = noise + 2 * ((long long)j * sh.nlm + idx);
+        const double re = (double)nz[0];
+        const double im = m0 ? 0.0 : (double)nz[1];
+        neumaier(s[0], c[0], VT[j] * re);
+        neumaier(s[1], c[1], VT[j] * im);
+        neumaier(s[2], c[2], VE[j] * re);
+        neumaier(s[3], c[3], VE[j] * im);
+    }
+    aL[idx] = make_double2(s[0] + c[0], s[1] + c[1]);
+    aL[sh.nlm + idx] = make_double2(s[2] + c[2], s[3] + c[3]);
+}
+
+// -------------------------------------------------------- Legendre synthesis
+
+// Block = (m, 64 ring pairs, column tile of 16 CF columns); wave w owns 16
+// pairs.  The contraction index is l in steps of 8: four even and four odd
+// l - m per step.  Every lane runs the FP64 recurrence for its pair (lane
+// mod 16) and keeps the value its MFMA k-slot (lane / 16) needs; the
+// coefficient loads are wave-uniform.
+template <typename T, int CF>
+__global__ __launch_bounds__(256) void k_synth(Shape sh, const double *__restrict__ x,
+                                               const double *__restrict__ lmm,
+                                               const double2 *__restrict__ coef,
+                                               const T *__restrict__ phi, T *__restrict__ G)
+{
+    using M = Mt<T>;
+    const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
+    const int npt = (npair + kPairTile - 1) / kPairTile;
+    int b = blockIdx.x;
+    const int ct = b % sh.nct;
+    b /= sh.nct;
+    const int pt = b % npt;
+    const int m = b / npt;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int p = pt * kPairTile + wave * 16 + i16;
+    const bool pv = p < npair;
+    const double xp = pv ? x[p] : 0.0;
+    double l1 = 0.0, l2 = pv ? lmm[(long long)m * npair + p] : 0.0;
+    typename M::acc acc[2][CF];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < CF; c++) acc[a][c] = typename M::acc{};
+    const long long rowm = mrow(L, m, m);
+    const int colb = ct * sh.CT + i16;
+    for (int l0 = m; l0 <= L; l0 += 8) {
+        double v[8];
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int l = l0 + q;
+            const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
+            const double nv = ab.x * xp * l1 - ab.y * l2;
+            v[q] = nv;
+            l2 = l1;
+            l1 = nv;
+        }
+        const double e = k4 == 0 ? v[0] : k4 == 1 ? v[2] : k4 == 2 ? v[4] : v[6];
+        const double o = k4 == 0 ? v[1] : k4 == 1 ? v[3] : k4 == 2 ? v[5] : v[7];
+        const int lE = l0 + 2 * k4, lO = lE + 1;
+        const T ae = (T)e, ao = (T)o;
+        const T *rE = phi + (rowm + (lE - m)) * Cpad;
+        const T *rO = rE + Cpad;
+#pragma unroll
+        for (int cf = 0; cf < CF; cf++) {
+            const int col = colb + 16 * cf;
+            const T bE = (lE <= L) ? rE[col] : T(0);
+            const T bO = (lO <= L) ? rO[col] : T(0);
+            acc[0][cf] = M::mfma(ae, bE, acc[0][cf]);
+            acc[1][cf] = M::mfma(ao, bO, acc[1][cf]);
+        }
+    }
+#pragma unroll
+    for (int par = 0; par < 2; par++)
+#pragma unroll
+        for (int cf = 0; cf < CF; cf++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int pair = pt * kPairTile + wave * 16 + M::row(k4, r);
+                if (pair < npair)
+                    G[(((long long)pair * (L + 1) + m) * 2 + par) * Cpad + colb + 16 * cf] =
+                        acc[par][cf][r];
+            }
+}
+
+// ------------------------------------------------------------- ring FFTs
+
+template <typename C2> __device__ inline C2 cmul(C2 a, C2 b)
+{
+    C2 r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+template <typename C2> __device__ inline C2 cadd(C2 a, C2 b)
+{
+    C2 r;
+    r.x = a.x + b.x;
+    r.y = a.y + b.y;
+    return r;
+}
+template <typename C2> __device__ inline C2 csub(C2 a, C2 b)
+{
+    C2 r;
+    r.x = a.x - b.x;
+    r.y = a.y - b.y;
+    return r;
+}
+// s * i * a with s = +1 or -1
+template <typename C2> __device__ inline C2 cmuli(C2 a, int s)
+{
+    C2 r;
+    r.x = s > 0 ? -a.y : a.y;
+    r.y = s > 0 ? a.x : -a.x;
+    return r;
+}
+
+// Radix-R DFT in place; forward uses e^{-2 pi i t k / R}, INV e^{+...}.
+template <typename C2, int R, bool INV> __device__ inline void dft_small(C2 *a)
+{
+    using T = decltype(a[0].x);
+    constexpr int sg = INV ? 1 : -1;  // sign of the exponent
+    if constexpr (R == 2) {
+        const C2 t = a[0];
+        a[0] = cadd(t, a[1]);
+        a[1] = csub(t, a[1]);
+    } else if constexpr (R == 3) {
+        const T h = (T)0.86602540378443864676372317075294;  // sqrt(3)/2
+        const C2 t1 = cadd(a[1], a[2]), t2 = csub(a[1], a[2]);
+        C2 mm;
+        mm.x = a[0].x - (T)0.5 * t1.x;
+        mm.y = a[0].y - (T)0.5 * t1.y;
+        C2 s2;
+        s2.x = h * t2.x;
+        s2.y = h * t2.y;
+        a[0] = cadd(a[0], t1);
+        a[1] = cadd(mm, cmuli(s2, sg));
+        a[2] = csub(mm, cmuli(s2, sg));
+    } else if constexpr (R == 4) {
+        const C2 t0 = cadd(a[0], a[2]), t1 = csub(a[0], a[2]);
+        const C2 t2 = cadd(a[1], a[3]), t3 = csub(a[1], a[3]);
+        a[0] = cadd(t0, t2);
+        a[2] = csub(t0, t2);
+        a[1] = cadd(t1, cmuli(t3, sg));
+        a[3] = csub(t1, cmuli(t3, sg));
+    } else {  // R == 5
+        const T c1 = (T)0.30901699437494742410229341718282;   // cos(2 pi/5)
+        const T c2 = (T)-0.80901699437494742410229341718282;  // cos(4 pi/5)
+        const T s1 = (T)0.95105651629515357211643933337938;   // sin(2 pi/5)
+        const T s2 = (T)0.58778525229247312916870595463907;   // sin(4 pi/5)
+        const C2 t1 = cadd(a[1], a[4]), t2 = cadd(a[2], a[3]);
+        const C2 t3 = csub(a[1], a[4]), t4 = csub(a[2], a[3]);
+        C2 b1, b2, d1, d2;
+        b1.x = a[0].x + c1 * t1.x + c2 * t2.x;
+        b1.y = a[0].y + c1 * t1.y + c2 * t2.y;
+        b2.x = a[0].x + c2 * t1.x + c1 * t2.x;
+        b2.y = a[0].y + c2 * t1.y + c1 * t2.y;
+        d1.x = s1 * t3.x + s2 * t4.x;
+        d1.y = s1 * t3.y + s2 * t4.y;
+        d2.x = s2 * t3.x - s1 * t4.x;
+        d2.y = s2 * t3.y - s1 * t4.y;
+        a[0] = cadd(a[0], cadd(t1, t2));
+        a[1] = cadd(b1, cmuli(d1, sg));
+        a[4] = csub(b1, cmuli(d1, sg));
+        a[2] = cadd(b2, cmuli(d2, sg));
+        a[3] = csub(b2, cmuli(d2, sg));
+    }
+}
+
+// One Stockham pass of radix R over the n-point array in LDS, 256 threads.
+// Butterfly i (k = i mod p) reads x_t = buf[i + t n/R], twists it by
+// w^{t k n/(p R)} and writes DFT_R(x)_t to buf[(i - k) R + k + t p].  All reads
+// finish before any write, so the pass works in place.
+template <typename C2, int R, bool INV>
+__device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
+{
+    constexpr int MAXB = (kMaxPhi / R + 255) / 256;
+    const int nb = n / R;
+    const int tstep = n / (p * R);
+    C2 y[MAXB][R];
+#pragma unroll
+    for (int c = 0; c < MAXB; c++) {
+        const int i = threadIdx.x + c * 256;
+        if (i < nb) {
+            const int k = i % p;
+            C2 xv[R];
+#pragma unroll
+            for (int t = 0; t < R; t++) xv[t] = buf[i + t * nb];
+#pragma unroll
+            for (int t = 1; t < R; t++) {
+                C2 w = tw[t * k * tstep];
+                if (INV) w.y = -w.y;
+                xv[t] = cmul(xv[t], w);
+            }
+            dft_small<C2, R, INV>(xv);
+#pragma unroll
+            for (int t = 0; t < R; t++) y[c][t] = xv[t];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < MAXB; c++) {
+        const int i = threadIdx.x + c * 256;
+        if (i < nb) {
+            const int k = i % p;
+            const int j = (i - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; t++) buf[j + t * p] = y[c][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename C2, bool INV>
+__device__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw)
+{
+    int p = 1;
+    for (int ps = 0; ps < sh.npass; ps++) {
+        const int R = sh.radix[ps];
+        if (R == 4)
+            fft_pass<C2, 4, INV>(buf, sh.nphi, p, tw);
+        else if (R == 2)
+            fft_pass<C2, 2, INV>(buf, sh.nphi, p, tw);
+        else if (R == 3)
+            fft_pass<C2, 3, INV>(buf, sh.nphi, p, tw);
+        else
+            fft_pass<C2, 5, INV>(buf, sh.nphi, p, tw);
+        p *= R;
+    }
+}
+
+// Block = (ring pair p, shell s).  The north and south rings travel together
+// as one complex sequence z = f_N + i f_S: spectrum Z_m = N_m + i S_m for
+// 0 <= m <= L and Z_{n-m} = conj(N_m) + i conj(S_m), with N = E + O and
+// S = E - O.  After the inverse FFT, w = f_N^2 + i f_S^2 goes through the
+// forward FFT and the two real spectra separate as (W_m + conj W_{n-m})/2 and
+// (W_m - conj W_{n-m})/(2i).  With n = 3L the DFT bin L also holds mode -2L
+// of the square, n conj(G_L)^2, which is subtracted.  Blocks are numbered so
+// that consecutive shells of one pair run on the same XCD (shared L2 lines).
+template <typename T>
+__global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict__ wq,
+                                              const typename Mt<T>::c2 *__restrict__ tw,
+                                              const T *__restrict__ G, T *__restrict__ F,
+                                              double *__restrict__ maps, int mode)
+{
+    using C2 = typename Mt<T>::c2;
+    extern __shared__ unsigned char smem_raw[];
+    C2 *buf = reinterpret_cast<C2 *>(smem_raw);
+    const int L = sh.L, n = sh.nphi, Cpad = sh.Cpad;
+    const int nblk = sh.npair * sh.N;
+    const int nslot = (nblk + 7) / 8;
+    const int logical = (blockIdx.x & 7) * nslot + (blockIdx.x >> 3);
+    if (logical >= nblk) return;
+    const int s = logical % sh.N, p = logical / sh.N;
+    const int tid = threadIdx.x;
+    const bool eq = sh.equator && p == sh.npair - 1;
+
+    for (int q = tid; q < n; q += 256) {
+        C2 z;
+        z.x = T(0);
+        z.y = T(0);
+        buf[q] = z;
+    }
+    __syncthreads();
+    const T *Gp = G + (long long)p * (L + 1) * 2 * Cpad + 2 * s;
+    for (int m = tid; m <= L; m += 256) {
+        const T *g = Gp + (long long)m * 2 * Cpad;
+        const T Er = g[0], Ei = g[1], Or = g[Cpad], Oi = g[Cpad + 1];
+        T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
+        if (eq) Sr = Si = T(0);
+        if (m == 0) Ni = Si = T(0);
+        C2 z;
+        z.x = Nr - Si;
+        z.y = Ni + Sr;
+        buf[m] = z;
+        if (m > 0) {
+            z.x = Nr + Si;
+            z.y = Sr - Ni;
+            buf[n - m] = z;
+        }
+    }
+    __syncthreads();
+    fft_lds<C2, true>(buf, sh, tw);
+    if (mode == 1) {
+        const long long nr = sh.nring;
+        for (int j = tid; j < n; j += 256) {
+            maps[((long long)s * nr + p) * n + j] = (double)buf[j].x;
+            if (!eq) maps[((long long)s * nr + (nr - 1 - p)) * n + j] = (double)buf[j].y;
+        }
+        return;
+    }
+    for (int j = tid; j < n; j += 256) {
+        C2 z = buf[j];
+        z.x = z.x * z.x;
+        z.y = z.y * z.y;
+        buf[j] = z;
+    }
+    __syncthreads();
+    fft_lds<C2, false>(buf, sh, tw);
+
+    const T wgt = (T)wq[p];
+    const T half = T(0.5);
+    for (int m = tid; m <= L; m += 256) {
+        const C2 W1 = buf[m];
+        const C2 W2 = buf[m == 0 ? 0 : n - m];
+        T Ar = half * (W1.x + W2.x), Ai = half * (W1.y - W2.y);
+        T Br = half * (W1.y + W2.y), Bi = -half * (W1.x - W2.x);
+        if (sh.alias && m == L) {
+            const T *g = Gp + (long long)L * 2 * Cpad;
+            const T Er = g[0], Ei = g[1], Or = g[Cpad], Oi = g[Cpad + 1];
+            T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
+            if (eq) Sr = Si = T(0);
+            const T fn = (T)n;
+            Ar -= fn * (Nr * Nr - Ni * Ni);
+            Ai -= fn * (-T(2) * Nr * Ni);
+            Br -= fn * (Sr * Sr - Si * Si);
+            Bi -= fn * (-T(2) * Sr * Si);
+        }
+        if (eq) Br = Bi = T(0);
+        T FEr = wgt * (Ar + Br), FEi = wgt * (Ai + Bi);
+        T FOr = wgt * (Ar - Br), FOi = wgt * (Ai - Bi);
+        if (eq) FOr = FOi = T(0);
+        if (m == 0) FEi = FOi = T(0);
+        T *f = F + ((long long)m * sh.npair + p) * 2 * Cpad + 2 * s;
+        f[0] = FEr;
+        f[1] = FEi;
+        f[Cpad] = FOr;
+        f[Cpad + 1] = FOi;
+    }
+}
+
+// --------------------------------------------------------- Legendre analysis
+
+// Block = (m, 128 l rows, column tile).  Wave w owns rows l0w .. l0w+31,
+// l0w = m + 128 t + 32 w: 16 rows with l - m even (against F_E) and 16 odd
+// (against F_O).  For each chunk of 64 ring pairs the wave runs the FP64
+// recurrence with one lane per pair, starting from the stored seeds at l0w,
+// stages the 32 x 64 values in LDS and reads them back in the MFMA A layout
+// (lane = (row, pair)).  mode 0 folds the radial sum into the epilogue:
+// part[ct][X][idx(l, m)] = sum_s W^X_ls Phi_NL,lm(s) over the tile's shells.
+template <typename T, int CF, int MODE>
+__global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__ tiles,
+                                              const double *__restrict__ x,
+                                              const double2 *__restrict__ coef,
+                                              const double2 *__restrict__ seed,
+                                              const int *__restrict__ seedoff,
+                                              const double *__restrict__ W,
+                                              const double *__restrict__ mu,
+                                              const T *__restrict__ F, double2 *__restrict__ part,
+                                              T *__restrict__ outphi)
+{
+    using M = Mt<T>;
+    __shared__ T lam[4][32][65];
+    const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
+    const int4 tl = tiles[blockIdx.x];
+    const int m = tl.x, lt = tl.y, ct = tl.z;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int l0w = m + lt * kLTile + wave * 32;
+    const bool wact = l0w <= L;
+    const long long rowm = mrow(L, m, m);
+    const long long srow = (long long)seedoff[m] + (wact ? (l0w - m) / kSeedStride : 0);
+    typename M::acc acc[2][CF];
+#pragma unroll
+    for (int a = 0; a < 2; a++)
+#pragma unroll
+        for (int c = 0; c < CF; c++) acc[a][c] = typename M::acc{};
+    const int colb = ct * sh.CT + i16;
+    const int nchunk = (npair + 63) / 64;
+    for (int pc = 0; pc < nchunk; pc++) {
+        const int p = pc * 64 + lane;
+        const bool pv = wact && p < npair;
+        double a0 = 0.0, a1 = 0.0, xp = 0.0;
+        if (pv) {
+            const double2 sd = seed[srow * npair + p];
+            a0 = sd.x;
+            a1 = sd.y;
+            xp = x[p];
+        }
+        lam[wave][0][lane] = (T)a0;
+        lam[wave][1][lane] = (T)a1;
+#pragma unroll 6
+        for (int q = 2; q < 32; q++) {
+            const int l = l0w + q;
+            const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
+            const double v = ab.x * xp * a1 - ab.y * a0;
+            lam[wave][q][lane] = (T)v;
+            a0 = a1;
+            a1 = v;
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int kk = 0; kk < 16; kk++) {
+            const T aE = lam[wave][2 * i16][4 * kk + k4];
+            const T aO = lam[wave][2 * i16 + 1][4 * kk + k4];
+            const int pp = pc * 64 + 4 * kk + k4;
+            const T *f = F + ((long long)m * npair + pp) * 2 * Cpad + colb;
+            const bool ok = pp < npair;
+#pragma unroll
+            for (int cf = 0; cf < CF; cf++) {
+                const T bE = ok ? f[16 * cf] : T(0);
+                const T bO = ok ? f[Cpad + 16 * cf] : T(0);
+                acc[0][cf] = M::mfma(aE, bE, acc[0][cf]);
+                acc[1][cf] = M::mfma(aO, bO, acc[1][cf]);
+            }
+        }
+        __syncthreads();
+    }
+
+    const int Npad = Cpad / 2;
+#pragma unroll
+    for (int par = 0; par < 2; par++)
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int l = l0w + 2 * M::row(k4, r) + par;
+            const bool lok = wact && l <= L;
+            double sT = 0.0, sE = 0.0;
+#pragma unroll
+            for (int cf = 0; cf < CF; cf++) {
+                const int col = colb + 16 * cf;
+                const int s = col >> 1;
+                double v = (double)acc[par][cf][r];
+                if (m == 0 && l == 0) {
+                    if (sh.mean_mode == 0)
+                        v = 0.0;
+                    else if ((col & 1) == 0)
+                        v -= mu[s];
+                }
+                if (MODE == 0) {
+                    if (lok) {
+                        sT += W[(long long)l * Npad + s] * v;
+                        sE += W[(long long)(L + 1 + l) * Npad + s] * v;
+                    }
+                } else if (lok) {
+                    outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
+                }
+            }
+            if (MODE == 0) {
+                sT += __shfl_xor(sT, 2);
+                sT += __shfl_xor(sT, 4);
+                sT += __shfl_xor(sT, 8);
+                sE += __shfl_xor(sE, 2);
+                sE += __shfl_xor(sE, 4);
+                sE += __shfl_xor(sE, 8);
+                if (lok && i16 < 2) {
+                    const long long id = lm_index(l, m);
+                    double *pT = reinterpret_cast<double *>(part + ((long long)ct * 2) * sh.nlm + id);
+                    double *pE =
+                        reinterpret_cast<double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
+                    pT[i16] = (m == 0 && i16 == 1) ? 0.0 : sT;
+                    pE[i16] = (m == 0 && i16 == 1) ? 0.0 : sE;
+                }
+            }
+        }
+}
+
+// -------------------------------------------------------------- combine
+
+__global__ __launch_bounds__(256) void k_combine(Shape sh, const double2 *__restrict__ part,
+                                                 const double2 *__restrict__ aL, double fnl,
+                                                 double2 *__restrict__ aT, double2 *__restrict__ aE,
+                                                 double2 *__restrict__ aTn,
+                                                 double2 *__restrict__ aEn)
+{
+    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= sh.nlm) return;
+    const int l = l_of_index(idx);
+    const bool m0 = lm_index(l, 0) == idx;
+#pragma unroll
+    for (int X = 0; X < 2; X++) {
+        double sr = 0, cr = 0, si = 0, ci = 0;
+        for (int ct = 0; ct < sh.nct; ct++) {
+            const double2 v = part[((long long)ct * 2 + X) * sh.nlm + idx];
+            neumaier(sr, cr, v.x);
+            neumaier(si, ci, v.y);
+        }
+        double2 nl = make_double2(sr + cr, m0 ? 0.0 : si + ci);
+        const double2 lin = aL[(long long)X * sh.nlm + idx];
+        double2 tot = make_double2(lin.x + fnl * nl.x, m0 ? 0.0 : lin.y + fnl * nl.y);
+        if (X == 0) {
+            aT[idx] = tot;
+            if (aTn) aTn[idx] = nl;
+        } else {
+            aE[idx] = tot;
+            if (aEn) aEn[idx] = nl;
+        }
+    }
+}
+
+// --------------------------------------------------------- recurrence seeds
+
+// One thread per (m, pair): run lambda_lm(x_p) up l and store
+// (lambda_l0, lambda_l0+1) at every l0 = m + 32 u.
+__global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__restrict__ x,
+                                                   const double *__restrict__ lmm,
+                                                   const double2 *__restrict__ coef,
+                                                   const int *__restrict__ seedoff,
+                                                   double2 *__restrict__ seed)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const int npair = sh.npair, L = sh.L;
+    if (t >= (long long)(L + 1) * npair) return;
+    const int p = (int)(t % npair), m = (int)(t / npair);
+    const double xp = x[p];
+    double l1 = 0.0, l2 = lmm[(long long)m * npair + p];
+    const long long rowm = mrow(L, m, m);
+    double pending = 0.0;
+    for (int l = m; l <= L; l++) {
+        const double2 ab = coef[rowm + (l - m)];
+        const double v = ab.x * xp * l1 - ab.y * l2;
+        l2 = l1;
+        l1 = v;
+        const int d = l - m;
+        if (d % kSeedStride == 0) pending = v;
+        if (d % kSeedStride == 1)
+            seed[((long long)seedoff[m] + d / kSeedStride) * npair + p] = make_double2(pending, v);
+    }
+    if ((L - m) % kSeedStride == 0)
+        seed[((long long)seedoff[m] + (L - m) / kSeedStride) * npair + p] =
+            make_double2(pending, 0.0);
+}
+
+// ---------------------------------------------------------- layout helpers
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_phi_to_api(Shape sh, const T *__restrict__ phi,
+                                                    double2 *__restrict__ api)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sh.nlm * sh.N) return;
+    const long long idx = t % sh.nlm;
+    const int s = (int)(t / sh.nlm);
+    const int l = l_of_index(idx);
+    const int m = (int)(idx - lm_index(l, 0));
+    const T *src = phi + mrow(sh.L, m, l) * sh.Cpad + 2 * s;
+    api[t] = make_double2((double)src[0], m == 0 ? 0.0 : (double)src[1]);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_api_to_phi(Shape sh, const double2 *__restrict__ api,
+                                                    T *__restrict__ phi)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sh.nlm * sh.N) return;
+    const long long idx = t % sh.nlm;
+    const int s = (int)(t / sh.nlm);
+    const int l = l_of_index(idx);
+    const int m = (int)(idx - lm_index(l, 0));
+    T *dst = phi + mrow(sh.L, m, l) * sh.Cpad + 2 * s;
+    const double2 v = api[t];
+    dst[0] = (T)v.x;
+    dst[1] = m == 0 ? T(0) : (T)v.y;
+}
+
+// ------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s)
+{
+    const long long n = (long long)(sh.L + 1) * sh.npair;
+    hipLaunchKernelGGL(k_seed_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, sh, b.x, b.lmm,
+                       b.coef, b.seedoff, b.seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
+                         hipStream_t s)
+{
+    dim3 grid(b.nk1, b.Mpad / 64);
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_filter<float>, grid, dim3(256), 0, s, sh, (const float *)b.FT, b.Kpad,
+                           b.Mpad, b.k1tiles, (const float *)noise, (float *)phi_out);
+    else
+        hipLaunchKernelGGL(k_filter<double>, grid, dim3(256), 0, s, sh, (const double *)b.FT,
+                           b.Kpad, b.Mpad, b.k1tiles, (const double *)noise, (double *)phi_out);
+    return hipGetLastError();
+}
+
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s)
+{
+    dim3 grid(blocks_for(sh.nlm, 256));
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_radial_lin<float>, grid, dim3(256), 0, s, sh, b.V,
+                           (const float *)noise, b.aL);
+    else
+        hipLaunchKernelGGL(k_radial_lin<double>, grid, dim3(256), 0, s, sh, b.V,
+                           (const double *)noise, b.aL);
+    return hipGetLastError();
+}
+
+template <typename T, int CF>
+static void synth_t(const Shape &sh, const Bufs &b, const void *phi, void *G, hipStream_t s)
+{
+    const int npt = (sh.npair + kPairTile - 1) / kPairTile;
+    dim3 grid((unsigned)((long long)(sh.L + 1) * npt * sh.nct));
+    hipLaunchKernelGGL((k_synth<T, CF>), grid, dim3(256), 0, s, sh, b.x, b.lmm, b.coef,
+                       (const T *)phi, (T *)G);
+}
+
+template <typename T>
+static void synth_cf(const Shape &sh, const Bufs &b, const void *phi, void *G, hipStream_t s)
+{
+    switch (sh.CF) {
+    case 1: synth_t<T, 1>(sh, b, phi, G, s); break;
+    case 2: synth_t<T, 2>(sh, b, phi, G, s); break;
+    case 3: synth_t<T, 3>(sh, b, phi, G, s); break;
+    case 4: synth_t<T, 4>(sh, b, phi, G, s); break;
+    default: synth_t<T, 5>(sh, b, phi, G, s); break;
+    }
+}
+
+hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
+                        hipStream_t s)
+{
+    if (sh.fp32)
+        synth_cf<float>(sh, b, phi_in, G_out, s);
+    else
+        synth_cf<double>(sh, b, phi_in, G_out, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                       double *maps, int mode, hipStream_t s)
+{
+    const long long nblk = (long long)sh.npair * sh.N;
+    dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
+    if (sh.fp32) {
+        const size_t lds = sizeof(float2) * sh.nphi;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_ring<float>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_ring<float>, grid, dim3(256), lds, s, sh, b.wq,
+                           (const float2 *)b.tw, (const float *)G_in, (float *)F_out, maps, mode);
+    } else {
+        const size_t lds = sizeof(double2) * sh.nphi;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_ring<double>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_ring<double>, grid, dim3(256), lds, s, sh, b.wq,
+                           (const double2 *)b.tw, (const double *)G_in, (double *)F_out, maps,
+                           mode);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int CF>
+static void anal_t(const Shape &sh, const Bufs &b, const void *F, void *out, int mode,
+                   hipStream_t s)
+{
+    dim3 grid(b.nk4);
+    if (mode == 0)
+        hipLaunchKernelGGL((k_anal<T, CF, 0>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
+                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out);
+    else
+        hipLaunchKernelGGL((k_anal<T, CF, 1>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
+                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out);
+}
+
+template <typename T>
+static void anal_cf(const Shape &sh, const Bufs &b, const void *F, void *out, int mode,
+                    hipStream_t s)
+{
+    switch (sh.CF) {
+    case 1: anal_t<T, 1>(sh, b, F, out, mode, s); break;
+    case 2: anal_t<T, 2>(sh, b, F, out, mode, s); break;
+    case 3: anal_t<T, 3>(sh, b, F, out, mode, s); break;
+    case 4: anal_t<T, 4>(sh, b, F, out, mode, s); break;
+    default: anal_t<T, 5>(sh, b, F, out, mode, s); break;
+    }
+}
+
+hipError_t launch_anal(const Shape &sh, const Bufs &b, const void *F_in, void *out_phi, int mode,
+                       hipStream_t s)
+{
+    if (sh.fp32)
+        anal_cf<float>(sh, b, F_in, out_phi, mode, s);
+    else
+        anal_cf<double>(sh, b, F_in, out_phi, mode, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const Shape &sh, const Bufs &b, double fnl, double2 *aT, double2 *aE,
+                          double2 *aTn, double2 *aEn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_combine, dim3(blocks_for(sh.nlm, 256)), dim3(256), 0, s, sh, b.part,
+                       b.aL, fnl, aT, aE, aTn, aEn);
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_to_api(const Shape &sh, const void *phi, double2 *api, hipStream_t s)
+{
+    dim3 grid(blocks_for(sh.nlm * sh.N, 256));
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_phi_to_api<float>, grid, dim3(256), 0, s, sh, (const float *)phi, api);
+    else
+        hipLaunchKernelGGL(k_phi_to_api<double>, grid, dim3(256), 0, s, sh, (const double *)phi,
+                           api);
+    return hipGetLastError();
+}
+
+hipError_t launch_api_to_phi(const Shape &sh, const double2 *api, void *phi, hipStream_t s)
+{
+    dim3 grid(blocks_for(sh.nlm * sh.N, 256));
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_api_to_phi<float>, grid, dim3(256), 0, s, sh, api, (float *)phi);
+    else
+        hipLaunchKernelGGL(k_api_to_phi<double>, grid, dim3(256), 0, s, sh, api, (double *)phi);
+    return hipGetLastError();
+}
+
+}  // namespace fnl

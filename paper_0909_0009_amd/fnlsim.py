@@ -1,0 +1,259 @@
+"""ctypes binding of libfnlsim.so (include/fnlsim.h).
+
+Argument marshalling only: every step of the map generator runs in the HIP
+library.  torch provides device memory and the stream.  If the library is
+not built this module raises instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfnlsim.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
+SIM_FP64, SIM_FP32 = 0, 1
+SIM_MEAN_SAMPLE, SIM_MEAN_ENSEMBLE = 0, 1
+SIM_STAGE_FILTER, SIM_STAGE_NONLIN, SIM_STAGE_MAPS = 1, 2, 3
+
+SIM_NSTAGE = 6
+STAGE_NAMES = ("radial_lin", "filter", "synth", "ring", "anal", "combine")
+
+EXPORTS = ("sim_init", "sim_forward", "sim_backward", "sim_debug_stage", "sim_get_info",
+           "sim_profile", "sim_profile_read",
+           "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
+           "sim_destroy", "sim_last_error")
+
+_PRECISION = {"fp64": SIM_FP64, "fp32": SIM_FP32}
+_MEAN = {"sample": SIM_MEAN_SAMPLE, "ensemble": SIM_MEAN_ENSEMBLE}
+
+
+class SimError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fnlsim error {code}: {msg}")
+        self.code = code
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("n_ring", ctypes.c_int), ("n_phi", ctypes.c_int), ("precision", ctypes.c_int),
+                ("mean_mode", ctypes.c_int), ("max_batch", ctypes.c_int),
+                ("stream", ctypes.c_void_p)]
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("lmax", ctypes.c_int), ("nshell", ctypes.c_int), ("n_ring", ctypes.c_int),
+                ("n_phi", ctypes.c_int), ("n_pair", ctypes.c_int), ("precision", ctypes.c_int),
+                ("mean_mode", ctypes.c_int), ("n_lm", ctypes.c_longlong),
+                ("workspace_bytes", ctypes.c_longlong)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfnlsim.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "python -m paper_0909_0009_amd.build (or __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, ip, dp = ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_double)
+        L.sim_init.argtypes = [ctypes.POINTER(vp), ip, ip, vp, vp, vp, vp, vp,
+                               ctypes.POINTER(_Opts)]
+        L.sim_init.restype = ip
+        L.sim_forward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
+        L.sim_forward.restype = ip
+        L.sim_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
+        L.sim_backward.restype = ip
+        L.sim_debug_stage.argtypes = [vp, ip, vp, vp]
+        L.sim_debug_stage.restype = ip
+        L.sim_profile.argtypes = [vp, ip]
+        L.sim_profile.restype = ip
+        L.sim_profile_read.argtypes = [vp, vp, vp, ip]
+        L.sim_profile_read.restype = ip
+        L.sim_get_info.argtypes = [vp, ctypes.POINTER(_Info)]
+        L.sim_get_info.restype = ip
+        L.sim_get_grid.argtypes = [vp, vp, vp]
+        L.sim_get_grid.restype = ip
+        L.sim_batch_create.argtypes = [vp, ip, ctypes.POINTER(vp)]
+        L.sim_batch_create.restype = ip
+        L.sim_batch_forward.argtypes = [vp, vp, vp, vp, vp]
+        L.sim_batch_forward.restype = ip
+        L.sim_batch_destroy.argtypes = [vp]
+        L.sim_batch_destroy.restype = ip
+        L.sim_destroy.argtypes = [vp]
+        L.sim_destroy.restype = ip
+        L.sim_last_error.argtypes = [vp]
+        L.sim_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _check(rc, ctx):
+    if rc != SIM_OK:
+        raise SimError(rc, lib().sim_last_error(ctx).decode())
+
+
+def nlm(L):
+    return (L + 1) * (L + 2) // 2
+
+
+class Simulator:
+    """One context of the map generator (see include/fnlsim.h)."""
+
+    def __init__(self, lmax, r, w, filt, alpha, beta, n_ring=0, n_phi=0, precision="fp64",
+                 mean="sample", stream=None):
+        self.lmax = int(lmax)
+        r, w, filt, alpha, beta = map(_f64, (r, w, filt, alpha, beta))
+        self.nshell = int(r.shape[0])
+        N, L = self.nshell, self.lmax
+        if filt.shape != (L + 1, N, N) or alpha.shape != (L + 1, N) or beta.shape != (L + 1, N):
+            raise ValueError("filter must be [L+1][N][N], alpha/beta [L+1][N]")
+        self.precision = precision
+        self.noise_dtype = torch.complex128 if precision == "fp64" else torch.complex64
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        opts = _Opts(int(n_ring), int(n_phi), _PRECISION[precision], _MEAN[mean], 0,
+                     ctypes.c_void_p(stream) if stream else None)
+        h = ctypes.c_void_p()
+        rc = lib().sim_init(ctypes.byref(h), L, N, r.ctypes.data, w.ctypes.data,
+                            filt.ctypes.data, alpha.ctypes.data, beta.ctypes.data,
+                            ctypes.byref(opts))
+        _check(rc, None)
+        self._h = h
+        info = _Info()
+        _check(lib().sim_get_info(self._h, ctypes.byref(info)), self._h)
+        self.n_ring, self.n_phi, self.n_pair = info.n_ring, info.n_phi, info.n_pair
+        self.n_lm = int(info.n_lm)
+        self.workspace_bytes = int(info.workspace_bytes)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def profile(self, enable=True):
+        _check(lib().sim_profile(self._h, 1 if enable else 0), self._h)
+
+    def profile_read(self):
+        """{stage: (total_ms, launches)} since the last read (synchronises)."""
+        ms = np.zeros(SIM_NSTAGE)
+        n = np.zeros(SIM_NSTAGE, dtype=np.int64)
+        _check(lib().sim_profile_read(self._h, ms.ctypes.data, n.ctypes.data, SIM_NSTAGE), self._h)
+        return {STAGE_NAMES[k]: (float(ms[k]), int(n[k])) for k in range(SIM_NSTAGE)}
+
+    def grid(self):
+        x = np.empty(self.n_ring)
+        w = np.empty(self.n_ring)
+        _check(lib().sim_get_grid(self._h, x.ctypes.data, w.ctypes.data), self._h)
+        return x, w
+
+    def _noise(self, noise):
+        if noise.dtype != self.noise_dtype or not noise.is_cuda:
+            raise TypeError(f"noise must be a CUDA tensor of dtype {self.noise_dtype}")
+        noise = noise.contiguous()
+        if noise.dim() == 2:
+            noise = noise.unsqueeze(0)
+        if tuple(noise.shape[1:]) != (self.nshell, self.n_lm):
+            raise ValueError(f"noise must be [R][{self.nshell}][{self.n_lm}]")
+        return noise
+
+    def forward(self, noise, fnl, want_nl=False):
+        """noise: [R][N][n_lm] (or [N][n_lm]) CUDA complex tensor.  Returns
+        (aT, aE) or (aT, aE, aT_nl, aE_nl), each [R][n_lm] complex128."""
+        noise = self._noise(noise)
+        R = noise.shape[0]
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(fnl, dtype=np.float64), (R,)))
+        dev = noise.device
+        aT = torch.empty((R, self.n_lm), dtype=torch.complex128, device=dev)
+        aE = torch.empty_like(aT)
+        aTn = torch.empty_like(aT) if want_nl else None
+        aEn = torch.empty_like(aT) if want_nl else None
+        rc = lib().sim_forward(self._h, noise.data_ptr(), R, f.ctypes.data, aT.data_ptr(),
+                               aE.data_ptr(), aTn.data_ptr() if want_nl else None,
+                               aEn.data_ptr() if want_nl else None)
+        _check(rc, self._h)
+        return (aT, aE, aTn, aEn) if want_nl else (aT, aE)
+
+    def backward(self, noise, fnl, gT, gE):
+        """Cotangents gT, gE [R][n_lm] complex128 -> (grad_noise, grad_fnl)."""
+        noise = self._noise(noise)
+        R = noise.shape[0]
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(fnl, dtype=np.float64), (R,)))
+        gT = gT.to(torch.complex128).contiguous().reshape(R, self.n_lm)
+        gE = gE.to(torch.complex128).contiguous().reshape(R, self.n_lm)
+        gn = torch.empty_like(noise)
+        gf = np.zeros(R)
+        rc = lib().sim_backward(self._h, noise.data_ptr(), R, f.ctypes.data, gT.data_ptr(),
+                                gE.data_ptr(), gn.data_ptr(), gf.ctypes.data)
+        _check(rc, self._h)
+        return gn, gf
+
+    def debug_stage(self, stage, inp):
+        dev = inp.device
+        if stage == SIM_STAGE_FILTER:
+            inp = self._noise(inp)[0]
+            out = torch.empty((self.nshell, self.n_lm), dtype=torch.complex128, device=dev)
+        elif stage == SIM_STAGE_NONLIN:
+            inp = inp.to(torch.complex128).contiguous()
+            out = torch.empty((self.nshell, self.n_lm), dtype=torch.complex128, device=dev)
+        elif stage == SIM_STAGE_MAPS:
+            inp = inp.to(torch.complex128).contiguous()
+            out = torch.empty((self.nshell, self.n_ring, self.n_phi), dtype=torch.float64,
+                              device=dev)
+        else:
+            raise ValueError(stage)
+        _check(lib().sim_debug_stage(self._h, stage, inp.data_ptr(), out.data_ptr()), self._h)
+        return out
+
+
+class FnlSimFunction(torch.autograd.Function):
+    """(noise, fnl) -> (aT, aE) with the hand-written adjoint as backward.
+    noise: [R][N][n_lm] complex CUDA tensor; fnl: [R] float64 tensor."""
+
+    @staticmethod
+    def forward(ctx, sim, noise, fnl):
+        f = fnl.detach().cpu().numpy().astype(np.float64)
+        aT, aE = sim.forward(noise.detach(), f)
+        ctx.sim = sim
+        ctx.save_for_backward(noise.detach(), fnl.detach())
+        return aT, aE
+
+    @staticmethod
+    def backward(ctx, gT, gE):
+        noise, fnl = ctx.saved_tensors
+        sim = ctx.sim
+        if gT is None:
+            gT = torch.zeros((noise.shape[0], sim.n_lm), dtype=torch.complex128, device=noise.device)
+        if gE is None:
+            gE = torch.zeros_like(gT)
+        gn, gf = sim.backward(noise, fnl.cpu().numpy(), gT, gE)
+        return None, gn, torch.as_tensor(gf, dtype=fnl.dtype, device=fnl.device)
+
+
+def simulate(sim, noise, fnl):
+    """Differentiable forward: returns (aT, aE)."""
+    fnl = torch.as_tensor(fnl, dtype=torch.float64).reshape(-1)
+    if noise.dim() == 2:
+        noise = noise.unsqueeze(0)
+    if fnl.numel() == 1 and noise.shape[0] > 1:
+        fnl = fnl.expand(noise.shape[0]).clone()
+    return FnlSimFunction.apply(sim, noise, fnl)

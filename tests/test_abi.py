@@ -1,0 +1,112 @@
+"""CPU checks of the C ABI: the library loads, exports every entry point the
+header declares, and rejects bad arguments before any device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fs():
+    from paper_0909_0009_amd import build, fnlsim
+    if build.stale():
+        build.build()
+    fnlsim.lib()
+    return fnlsim
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "fnlsim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sim_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("sim_init", "sim_forward", "sim_backward", "sim_destroy", "sim_last_error"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(fs):
+    lib = ctypes.CDLL(fs.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(declared_functions()) == set(fs.EXPORTS)
+
+
+def _args(L=4, N=3):
+    r = np.linspace(13000, 15000, N)
+    w = np.ones(N)
+    F = np.broadcast_to(np.eye(N), (L + 1, N, N)).copy()
+    a = np.ones((L + 1, N))
+    return r, w, F, a, a.copy()
+
+
+def _init(fs, L, N, r, w, F, a, b, opts=None):
+    h = ctypes.c_void_p()
+    p = lambda x: None if x is None else x.ctypes.data
+    rc = fs.lib().sim_init(ctypes.byref(h), L, N, p(r), p(w), p(F), p(a), p(b),
+                           ctypes.byref(opts) if opts is not None else None)
+    return rc, h
+
+
+@pytest.mark.parametrize("case", ["lmax0", "nshell0", "null_filter", "nan_filter", "inf_r",
+                                  "few_rings", "short_ring", "bad_radix", "big_phi",
+                                  "bad_precision", "bad_mean"])
+def test_init_rejects_bad_arguments_without_device(fs, case):
+    L, N = 4, 3
+    r, w, F, a, b = _args(L, N)
+    opts = fs._Opts(0, 0, 0, 0, 0, None)
+    if case == "lmax0":
+        L = 0
+    elif case == "nshell0":
+        N = 0
+    elif case == "null_filter":
+        F = None
+    elif case == "nan_filter":
+        F[2, 1, 0] = np.nan
+    elif case == "inf_r":
+        r[1] = np.inf
+    elif case == "few_rings":
+        opts.n_ring = (3 * L + 2) // 2 - 1
+    elif case == "short_ring":
+        opts.n_phi = 3 * L - 1
+    elif case == "bad_radix":
+        opts.n_phi = 7 * L  # has a factor 7
+    elif case == "big_phi":
+        opts.n_phi = 9000
+    elif case == "bad_precision":
+        opts.precision = 7
+    elif case == "bad_mean":
+        opts.mean_mode = 3
+    rc, h = _init(fs, L, N, r, w, F, a, b, opts)
+    assert rc == fs.SIM_EINVAL
+    assert not h.value
+    msg = fs.lib().sim_last_error(None).decode()
+    assert msg and msg != "no error"
+
+
+def test_null_context_calls(fs):
+    L = fs.lib()
+    assert L.sim_destroy(None) == fs.SIM_OK
+    assert L.sim_forward(None, None, 1, None, None, None, None, None) == fs.SIM_EINVAL
+    assert L.sim_backward(None, None, 1, None, None, None, None, None) == fs.SIM_EINVAL
+    assert L.sim_debug_stage(None, 1, None, None) == fs.SIM_EINVAL
+    assert L.sim_get_info(None, None) == fs.SIM_EINVAL
+    h = ctypes.c_void_p()
+    assert L.sim_batch_create(None, 0, ctypes.byref(h)) == fs.SIM_EINVAL
+    assert L.sim_batch_destroy(None) == fs.SIM_OK
+
+
+def test_valid_init_without_gpu_reports_device_error(fs):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    r, w, F, a, b = _args()
+    rc, h = _init(fs, 4, 3, r, w, F, a, b)
+    assert rc == fs.SIM_EDEVICE
+    assert "device" in fs.lib().sim_last_error(None).decode().lower()
