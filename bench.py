@@ -1,0 +1,238 @@
+"""Benchmark of the local-f_NL map generator on one MI355X.
+
+One step = one full forward pass of the hot path (filter, Legendre synthesis,
+ring FFT stage with the square and mean removal, Legendre analysis, radial
+quadrature, combine) for one T+E realization at the paper-scale workload
+(lmax 1024, 200 radial nodes, 1537 x 3072 Gauss-Legendre grid).  The
+headline value is the FP32 matrix-core path (FP64 recurrence and radial
+sums); the FP64 path is measured on the same inputs and reported beside it.
+
+Prints one JSON line.  Inputs are seeded and synthetic (see
+paper_0909_0009_amd/inputs.py) and resident in HBM before timing starts.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "T+E map realizations/sec at lmax=1024 (mixed vs FP64 GPU path, same error)"
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBs": 8000.0,
+    "fp64_mfma_TFs": 78.6,
+    "fp32_mfma_TFs": 157.3,
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stage_work(sim, stage, precision):
+    """Algorithmic work of one launch of a stage: (bound, amount, unit)."""
+    L, N = sim.lmax, sim.nshell
+    nlm = (L + 1) * (L + 2) // 2
+    C = 2 * N
+    esize = 8 if precision == "fp64" else 4
+    if stage in ("synth", "anal"):
+        # every lambda_lm(x_p) multiplies each of the 2N real columns once
+        return "mfma", 2.0 * sim.n_pair * nlm * C, "flop"
+    if stage == "filter":
+        return "mfma", 4.0 * N * N * nlm, "flop"
+    if stage == "ring":
+        # read the synthesis spectra, write the analysis spectra (E and O)
+        return "hbm", 2.0 * sim.n_pair * (L + 1) * 2 * C * esize, "byte"
+    if stage == "radial_lin":
+        return "hbm", N * nlm * 2.0 * esize + 2 * nlm * 16.0, "byte"
+    return "hbm", 0.0, "byte"
+
+
+def roofline(sim, stages, precision, steps):
+    """Roofline object for the stage with the largest total time."""
+    dom = max(stages, key=lambda k: stages[k][0])
+    tot_ms, n = stages[dom]
+    avg_s = tot_ms / max(n, 1) / 1e3
+    bound, work, unit = stage_work(sim, dom, precision)
+    if bound == "mfma":
+        achieved = work / avg_s / 1e12
+        peak = PEAK["fp64_mfma_TFs"] if precision == "fp64" else PEAK["fp32_mfma_TFs"]
+        u = "TFLOP/s"
+    else:
+        achieved = work / avg_s / 1e9
+        peak = PEAK["hbm_GBs"]
+        u = "GB/s"
+    return dom, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": u,
+                 "frac": round(achieved / peak, 4), "traffic": None,
+                 "kernel": dom, "avg_launch_ms": round(avg_s * 1e3, 4),
+                 "work_per_launch": work, "work_unit": unit}
+
+
+def time_path(torch, fnlsim, p, cfg, noise_np, precision, steps, warmup):
+    L, N = cfg["lmax"], cfg["nshell"]
+    sim = fnlsim.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                           n_ring=cfg["ntheta"], n_phi=cfg["nphi"], precision=precision)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    noise = torch.from_numpy(noise_np).to(dt).cuda()
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        out = sim.forward(noise, cfg["fnl"])
+    torch.cuda.synchronize()
+    sim.profile(True)
+    sim.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(steps):
+        out = sim.forward(noise, cfg["fnl"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    stages = sim.profile_read()
+    sim.profile(False)
+    aT, aE = out
+    res = dict(ms=ms, stages=stages, aT=aT.cpu().numpy().ravel(), aE=aE.cpu().numpy().ravel(),
+               sim=sim, ws=sim.workspace_bytes)
+    del noise
+    return res
+
+
+def per_l_rel_err(a, ref, L):
+    import numpy as np
+    ls = np.repeat(np.arange(L + 1), np.arange(1, L + 2))
+    ms = np.arange(ls.size) - ls * (ls + 1) // 2
+    c = np.where(ms == 0, 1.0, 2.0)
+    num = np.sqrt(np.bincount(ls, weights=c * np.abs(a - ref) ** 2))
+    den = np.sqrt(np.bincount(ls, weights=c * np.abs(ref) ** 2))
+    ok = den > 1e-12 * den.max()
+    return float(np.max(num[ok] / den[ok]))
+
+
+def cpu_baseline(p, cfg, noise_np, nsample):
+    """The FP64 oracle as it stands, on `nsample` of the N shells (transfer
+    tables zeroed elsewhere: the oracle then evaluates only those shells).
+    Work per shell is identical, so maps/s = 1 / (t * N / nsample)."""
+    import numpy as np
+    from oracle import fnl_oracle
+    L, N = cfg["lmax"], cfg["nshell"]
+    keep = np.linspace(N // 4, 3 * N // 4, nsample).astype(int)
+    al = np.zeros_like(p["alpha"])
+    be = np.zeros_like(p["beta"])
+    al[:, keep] = p["alpha"][:, keep]
+    be[:, keep] = p["beta"][:, keep]
+    P = fnl_oracle.Problem(L, p["r"], p["w"], p["filter"], al, be)
+    fnl_oracle.lib()
+    t0 = time.perf_counter()
+    P.forward(noise_np, cfg["fnl"])
+    t = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+    return {"value": 1.0 / (t * N / nsample), "unit": "maps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{nsample} of {N} shells at lmax {L} (filter rows, synthesis, square, "
+                      f"analysis and radial sums of those shells) in {t:.1f} s, scaled by "
+                      f"{N}/{nsample}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="paper", choices=["paper", "medium", "grad", "tiny"])
+    ap.add_argument("--cpu-shells", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB first (counter calibration)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the map generator runs on a single MI355X here; "
+              "realizations shard across GPUs with no communication, so N > 1 is not measured.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0909_0009_amd import fnlsim, inputs
+
+    if args.calib_copy_mb:
+        # a plain copy of known size: reads and writes exactly nbytes each
+        nbytes = args.calib_copy_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read and written")
+        del src, dst
+
+    cfg = dict(inputs.CONFIGS[args.workload])
+    L, N = cfg["lmax"], cfg["nshell"]
+    t0 = time.time()
+    p = inputs.problem(L, N)
+    noise_np = inputs.noise(L, N, inputs.realization_seed(0))
+    log(f"inputs ready in {time.time() - t0:.1f} s")
+
+    r32 = time_path(torch, fnlsim, p, cfg, noise_np, "fp32", args.steps, args.warmup)
+    log(f"fp32: {r32['ms']:.3f} ms/step")
+    dom, roof = roofline(r32["sim"], r32["stages"], "fp32", args.steps)
+    stages32 = {k: round(v[0] / max(v[1], 1), 4) for k, v in r32["stages"].items()}
+    r32["sim"].close()
+    torch.cuda.empty_cache()
+    fp64 = None
+    err = None
+    if not args.fp32_only:
+        r64 = time_path(torch, fnlsim, p, cfg, noise_np, "fp64", args.steps, args.warmup)
+        log(f"fp64: {r64['ms']:.3f} ms/step")
+        dom64, roof64 = roofline(r64["sim"], r64["stages"], "fp64", args.steps)
+        fp64 = {"value": round(1000.0 / r64["ms"], 4), "ms_per_step": round(r64["ms"], 4),
+                "shells_per_s": round(1000.0 / r64["ms"] * N, 2),
+                "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["stages"].items()},
+                "roofline": roof64}
+        # error of the mixed path against the FP64 GPU path (which matches the
+        # FP64 oracle to <= 1e-10 at this workload)
+        err = max(per_l_rel_err(r32["aT"], r64["aT"], L), per_l_rel_err(r32["aE"], r64["aE"], L))
+        r64["sim"].close()
+        torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(p, cfg, noise_np, args.cpu_shells)
+        log(f"cpu baseline: {cpu['value']:.3e} maps/s on {cpu['cores']} threads")
+
+    value = 1000.0 / r32["ms"]
+    line = {
+        "metric": METRIC,
+        "value": round(value, 4),
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: lmax={L}, {N} radial nodes, "
+                               f"{cfg['ntheta']}x{cfg['nphi']} Gauss-Legendre grid, "
+                               f"1 T+E realization per step, f_NL={cfg['fnl']}",
+                   "precision": "fp32 matrix cores; fp64 recurrence, mean and radial sums"},
+        "shells_per_s": round(value * N, 2),
+        "stages_ms": stages32,
+        "roofline": roof,
+        "fp64": fp64,
+        "mixed_vs_fp64_max_rel_err": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -487,9 +487,12 @@ int orc_adjoint(const orc_problem *P, const double *noise, double fnl,
     double *WE = (double *)malloc(sizeof(double) * (L + 1) * N);
     radial_weights(P, WT, WE);
 
-    double *phiL = (double *)malloc(sizeof(double) * 2 * nlm * N);
-    orc_filter(P, noise, phiL);
-    double *pbar = (double *)malloc(sizeof(double) * 2 * nlm * N);
+    /* a node whose radial weights are all zero receives no cotangent */
+    int *used = (int *)malloc(sizeof(int) * N);
+    for (int i = 0; i < N; i++) used[i] = shell_used(WT, WE, L, N, i);
+    double *phiL = (double *)calloc(2 * nlm * (size_t)N, sizeof(double));
+    filter_rows(P, noise, used, phiL);
+    double *pbar = (double *)calloc(2 * nlm * (size_t)N, sizeof(double));
 
     double *pixw = pixel_weights(nth, nph, wq);
     double *one_m = ones(L + 1);   /* c'_m = 1: each stored (l, m) once */
@@ -503,6 +506,7 @@ int orc_adjoint(const orc_problem *P, const double *noise, double fnl,
     size_t npix = (size_t)nth * nph;
 
     for (int i = 0; i < N; i++) {
+        if (!used[i]) continue;
         /* transposed radial sum */
         for (int l = 0; l <= L; l++) {
             double wt = WT[(size_t)l * N + i], we = WE[(size_t)l * N + i];
@@ -552,6 +556,7 @@ int orc_adjoint(const orc_problem *P, const double *noise, double fnl,
     }
     *grad_fnl = gf;
 
+    free(used);
     free(xs);
     free(dir);
     free(g);

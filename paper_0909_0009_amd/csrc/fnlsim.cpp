@@ -10,6 +10,7 @@
 // realization, on the context stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -42,8 +43,29 @@ struct sim_ctx {
     long long prof_n[SIM_NSTAGE] = {};
 };
 
+// A batch runs its contexts' forward passes as one grouped launch per stage
+// (per column-tile class for the Legendre kernels), captured once into a HIP
+// graph and replayed.  Per-call pointers travel in a small device array of
+// GroupItems copied in from pinned host memory before each replay.
 struct sim_batch {
     std::vector<sim_ctx *> ctxs;
+    int fp32 = 0;
+    hipStream_t user = nullptr;      // the contexts' stream (caller order)
+    hipStream_t bs = nullptr;        // batch stream (graphs cannot capture the null stream)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_copied = nullptr;
+    bool copied_pending = false;
+    fnl::GroupItem *items_host = nullptr;  // pinned
+    fnl::GroupItem *items_dev = nullptr;
+    int *plan_dev = nullptr;               // ord/off arrays of every launch
+    struct Launch {
+        int stage, CF, n, nblocks;
+        size_t lds;
+        int ord_off, off_off;              // offsets into plan_dev
+    };
+    std::vector<Launch> launches;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
 };
 
 namespace {
@@ -579,18 +601,61 @@ int sim_forward(sim_ctx *c, const void *noise, int R, const double *fnl, void *a
     return SIM_OK;
 }
 
+// Reverse pass for one realization (the steps of the forward transposed,
+// with Phi_L recomputed from the noise rather than stored).
+static int backward_one(sim_ctx *c, const void *noise, double fnl, const double2 *gT,
+                        const double2 *gE, void *grad, double *fbar_dev)
+{
+    const Shape &sh = c->sh;
+    const Bufs &b = c->b;
+    hipStream_t s = c->stream;
+    HIPCHECK(c, fnl::launch_radial_adj(sh, b, gT, gE, b.scratch, s));
+    HIPCHECK(c, fnl::launch_synth(sh, b, b.scratch, b.G2, s));
+    HIPCHECK(c, fnl::launch_filter(sh, b, noise, b.phi, s));
+    HIPCHECK(c, fnl::launch_synth(sh, b, b.phi, b.G, s));
+    HIPCHECK(c, fnl::launch_ring_adj(sh, b, b.G, b.G2, b.F, b.fpart, fnl, s));
+    HIPCHECK(c, fnl::launch_anal(sh, b, b.F, b.phi, 2, s, gT, gE));
+    HIPCHECK(c, fnl::launch_filter_t(sh, b, b.phi, grad, s));
+    HIPCHECK(c, fnl::launch_fbar(sh, b, b.fpart, gT, gE, fbar_dev, s));
+    return SIM_OK;
+}
+
 int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const void *gT,
                  const void *gE, void *grad_n, double *grad_fnl)
 {
     if (!c) return SIM_EINVAL;
-    (void)noise;
-    (void)R;
-    (void)fnl;
-    (void)gT;
-    (void)gE;
-    (void)grad_n;
-    (void)grad_fnl;
-    return fail(c, SIM_ESTATE, "sim_backward is not available in this build");
+    if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    if (!noise || !fnl || !gT || !gE || !grad_n || !grad_fnl)
+        return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    for (int r = 0; r < R; r++)
+        if (!std::isfinite(fnl[r])) return fail(c, SIM_EINVAL, "fnl[%d] is not finite", r);
+    const Shape &sh = c->sh;
+    Bufs &b = c->b;
+    int rc;
+    if (!b.G2) {
+        const size_t gb = (sh.fp32 ? 4 : 8) * (size_t)sh.npair * (sh.L + 1) * 2 * sh.Cpad;
+        if ((rc = alloc_zero(c, &b.G2, gb))) return rc;
+        void *p = nullptr;
+        if ((rc = alloc_zero(c, &p, sizeof(double) * (size_t)sh.npair * sh.N))) return rc;
+        b.fpart = (double *)p;
+    }
+    if (b.fbar_cap < R) {
+        void *p = nullptr;
+        if ((rc = alloc_zero(c, &p, sizeof(double) * (size_t)R))) return rc;
+        b.fbar = (double *)p;
+        b.fbar_cap = R;
+    }
+    const size_t nbytes = (sh.fp32 ? 8 : 16) * (size_t)sh.N * sh.nlm;
+    for (int r = 0; r < R; r++) {
+        rc = backward_one(c, (const char *)noise + nbytes * r, fnl[r],
+                          (const double2 *)gT + sh.nlm * r, (const double2 *)gE + sh.nlm * r,
+                          (char *)grad_n + nbytes * r, b.fbar + r);
+        if (rc) return rc;
+    }
+    HIPCHECK(c, hipMemcpyAsync(grad_fnl, b.fbar, sizeof(double) * R, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHECK(c, hipStreamSynchronize(c->stream));
+    return SIM_OK;
 }
 
 int sim_debug_stage(sim_ctx *c, int stage, const void *in, void *out)
@@ -624,6 +689,31 @@ int sim_debug_stage(sim_ctx *c, int stage, const void *in, void *out)
     return SIM_OK;
 }
 
+static int batch_fail(sim_batch *b, int code, const char *msg, hipError_t e)
+{
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s: %s", msg, hipGetErrorString(e));
+    if (b) b->err = buf;
+    g_init_err = buf;
+    return code;
+}
+
+int sim_batch_destroy(sim_batch *b)
+{
+    if (!b) return SIM_OK;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->ev_copied) (void)hipEventDestroy(b->ev_copied);
+    if (b->bs) (void)hipStreamDestroy(b->bs);
+    if (b->items_host) (void)hipHostFree(b->items_host);
+    if (b->items_dev) (void)hipFree(b->items_dev);
+    if (b->plan_dev) (void)hipFree(b->plan_dev);
+    delete b;
+    return SIM_OK;
+}
+
 int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
 {
     if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
@@ -631,27 +721,142 @@ int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
     if (!ctxs || count < 1) return fail(nullptr, SIM_EINVAL, "empty batch");
     for (int i = 0; i < count; i++)
         if (!ctxs[i]) return fail(nullptr, SIM_EINVAL, "context %d is NULL", i);
+    for (int i = 1; i < count; i++) {
+        if (ctxs[i]->sh.fp32 != ctxs[0]->sh.fp32)
+            return fail(nullptr, SIM_EINVAL, "contexts of one batch need the same precision");
+        if (ctxs[i]->stream != ctxs[0]->stream)
+            return fail(nullptr, SIM_EINVAL, "contexts of one batch need the same stream");
+    }
     sim_batch *b = new (std::nothrow) sim_batch();
     if (!b) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
     b->ctxs.assign(ctxs, ctxs + count);
+    b->fp32 = ctxs[0]->sh.fp32;
+    b->user = ctxs[0]->stream;
+
+    // contexts in decreasing lmax: the heaviest blocks are dispatched first
+    std::vector<int> order(count);
+    for (int i = 0; i < count; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) {
+        return ctxs[a]->sh.L > ctxs[c]->sh.L;
+    });
+    std::vector<int> plan;
+    auto add_launch = [&](int stage, int CF, const std::vector<int> &members) {
+        if (members.empty()) return;
+        sim_batch::Launch l{};
+        l.stage = stage;
+        l.CF = CF;
+        l.n = (int)members.size();
+        l.ord_off = (int)plan.size();
+        for (int m : members) plan.push_back(m);
+        l.off_off = (int)plan.size();
+        long long acc = 0;
+        size_t lds = 0;
+        for (int m : members) {
+            plan.push_back((int)acc);
+            const sim_ctx *c = ctxs[m];
+            acc += (fnl::group_blocks(stage, c->sh, c->b) + 7) / 8 * 8;
+            lds = std::max(lds, (c->sh.fp32 ? sizeof(float2) : sizeof(double2)) * (size_t)c->sh.nphi);
+        }
+        plan.push_back((int)acc);
+        l.nblocks = (int)acc;
+        l.lds = stage == fnl::GS_RING ? lds : 0;
+        b->launches.push_back(l);
+    };
+    for (int stage = 0; stage < fnl::GS_COUNT; stage++) {
+        if (stage == fnl::GS_SYNTH || stage == fnl::GS_ANAL) {
+            for (int cf = 5; cf >= 1; cf--) {
+                std::vector<int> mem;
+                for (int i : order)
+                    if (ctxs[i]->sh.CF == cf) mem.push_back(i);
+                add_launch(stage, cf, mem);
+            }
+        } else {
+            add_launch(stage, 0, order);
+        }
+    }
+    hipError_t e;
+    if ((e = hipMalloc((void **)&b->plan_dev, sizeof(int) * plan.size())) != hipSuccess ||
+        (e = hipMemcpy(b->plan_dev, plan.data(), sizeof(int) * plan.size(),
+                       hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMalloc((void **)&b->items_dev, sizeof(fnl::GroupItem) * count)) != hipSuccess ||
+        (e = hipHostMalloc((void **)&b->items_host, sizeof(fnl::GroupItem) * count,
+                           hipHostMallocDefault)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&b->bs, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->ev_copied, hipEventDisableTiming)) != hipSuccess) {
+        const int rc = batch_fail(b, SIM_EDEVICE, "batch set-up", e);
+        sim_batch_destroy(b);
+        return rc;
+    }
+    for (const auto &l : b->launches)
+        if (l.stage == fnl::GS_RING && (e = fnl::prepare_group_ring(b->fp32, l.lds)) != hipSuccess) {
+            const int rc = batch_fail(b, SIM_EDEVICE, "batch ring LDS", e);
+            sim_batch_destroy(b);
+            return rc;
+        }
+    for (int i = 0; i < count; i++) {
+        fnl::GroupItem &g = b->items_host[i];
+        memset(&g, 0, sizeof g);
+        g.sh = ctxs[i]->sh;
+        g.b = ctxs[i]->b;
+    }
     *out = b;
     return SIM_OK;
+}
+
+static hipError_t batch_launch_all(sim_batch *b, hipStream_t s)
+{
+    for (const auto &l : b->launches) {
+        const hipError_t e = fnl::launch_group(l.stage, b->fp32, l.CF, b->items_dev,
+                                               b->plan_dev + l.ord_off, b->plan_dev + l.off_off,
+                                               l.n, l.nblocks, l.lds, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 int sim_batch_forward(sim_batch *b, const void *const *noise, const double *fnl,
                       void *const *aT, void *const *aE)
 {
-    if (!b || !noise || !fnl || !aT || !aE) return SIM_EINVAL;
-    for (size_t i = 0; i < b->ctxs.size(); i++) {
-        const int rc = sim_forward(b->ctxs[i], noise[i], 1, fnl + i, aT[i], aE[i], nullptr, nullptr);
-        if (rc) return rc;
+    if (!b) return SIM_EINVAL;
+    if (!noise || !fnl || !aT || !aE) return batch_fail(b, SIM_EINVAL, "NULL argument", hipSuccess);
+    const int n = (int)b->ctxs.size();
+    for (int i = 0; i < n; i++)
+        if (!noise[i] || !aT[i] || !aE[i] || !std::isfinite(fnl[i]))
+            return batch_fail(b, SIM_EINVAL, "bad per-context argument", hipSuccess);
+    hipError_t e;
+    // the pinned staging buffer may still be read by the previous copy
+    if (b->copied_pending && (e = hipEventSynchronize(b->ev_copied)) != hipSuccess)
+        return batch_fail(b, SIM_EDEVICE, "batch staging", e);
+    for (int i = 0; i < n; i++) {
+        fnl::GroupItem &g = b->items_host[i];
+        g.noise = noise[i];
+        g.fnl = fnl[i];
+        g.aT = (double2 *)aT[i];
+        g.aE = (double2 *)aE[i];
     }
-    return SIM_OK;
-}
-
-int sim_batch_destroy(sim_batch *b)
-{
-    delete b;
+    if ((e = hipEventRecord(b->ev_in, b->user)) != hipSuccess ||
+        (e = hipStreamWaitEvent(b->bs, b->ev_in, 0)) != hipSuccess ||
+        (e = hipMemcpyAsync(b->items_dev, b->items_host, sizeof(fnl::GroupItem) * n,
+                            hipMemcpyHostToDevice, b->bs)) != hipSuccess ||
+        (e = hipEventRecord(b->ev_copied, b->bs)) != hipSuccess)
+        return batch_fail(b, SIM_EDEVICE, "batch upload", e);
+    b->copied_pending = true;
+    if (!b->exec) {
+        if ((e = hipStreamBeginCapture(b->bs, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+            return batch_fail(b, SIM_EDEVICE, "graph capture", e);
+        const hipError_t le = batch_launch_all(b, b->bs);
+        e = hipStreamEndCapture(b->bs, &b->graph);
+        if (le != hipSuccess) return batch_fail(b, SIM_EDEVICE, "graph capture launch", le);
+        if (e != hipSuccess) return batch_fail(b, SIM_EDEVICE, "graph capture end", e);
+        if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+            return batch_fail(b, SIM_EDEVICE, "graph instantiate", e);
+    }
+    if ((e = hipGraphLaunch(b->exec, b->bs)) != hipSuccess ||
+        (e = hipEventRecord(b->ev_out, b->bs)) != hipSuccess ||
+        (e = hipStreamWaitEvent(b->user, b->ev_out, 0)) != hipSuccess)
+        return batch_fail(b, SIM_EDEVICE, "graph launch", e);
     return SIM_OK;
 }
 

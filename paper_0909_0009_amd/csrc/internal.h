@@ -67,10 +67,38 @@ struct Bufs {
     double2 *part;     // [nct][2][nlm] per-column-tile radial sums of Phi_NL
     double2 *aL;       // [2][nlm] linear radial sums
     void *scratch;     // debug / backward staging, [nlm rows][Cpad] elements
+    void *G2;          // reverse pass: synthesis of the transposed radial sum (lazy)
+    double *fpart;     // reverse pass: [npair * N] per-block dLoss/df_NL shares (lazy)
+    double *fbar;      // reverse pass: [fbar_cap] dLoss/df_NL per realization (lazy)
+    int fbar_cap;
     int Kpad, Mpad;
     int nk1, nk4;
     long long nseedrow;
 };
+
+// One context inside a grouped (batch) launch: its shape and buffers plus the
+// per-call pointers of the current forward pass.
+struct GroupItem {
+    Shape sh;
+    Bufs b;
+    const void *noise;
+    double fnl;
+    double2 *aT, *aE;
+};
+
+// Stage ids of the grouped forward launches.
+enum { GS_RADIAL_LIN = 0, GS_FILTER, GS_SYNTH, GS_RING, GS_ANAL, GS_COMBINE, GS_COUNT };
+
+// Blocks of context `sh`/`b` in a stage (before rounding up to a multiple of 8).
+long long group_blocks(int stage, const Shape &sh, const Bufs &b);
+
+// One grouped launch: contexts ord[0..n) of `items` (device), block offsets
+// off[0..n] (device, multiples of 8), nblocks = off[n]; CF selects the
+// column-tile instantiation (synth/anal), lds the dynamic LDS (ring).
+hipError_t launch_group(int stage, int fp32, int CF, const GroupItem *items, const int *ord,
+                        const int *off, int n, int nblocks, size_t lds, hipStream_t s);
+// Raise the dynamic-LDS limit of the grouped ring kernel (call before capture).
+hipError_t prepare_group_ring(int fp32, size_t lds);
 
 // ----- launchers (kernels.hip); all asynchronous on `s`.
 hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);
@@ -83,10 +111,20 @@ hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void
 hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
                        double *maps, int mode, hipStream_t s);
 // mode 0: radial partial sums into b.part; 1: per-shell Phi_NL into out_phi.
+// mode 2: per-shell output plus sum_X W^X abar^X (reverse pass), into out_phi.
 hipError_t launch_anal(const Shape &sh, const Bufs &b, const void *F_in, void *out_phi, int mode,
-                       hipStream_t s);
+                       hipStream_t s, const double2 *gT = nullptr, const double2 *gE = nullptr);
 hipError_t launch_combine(const Shape &sh, const Bufs &b, double fnl, double2 *aT, double2 *aE,
                           double2 *aTn, double2 *aEn, hipStream_t s);
+// reverse pass
+hipError_t launch_radial_adj(const Shape &sh, const Bufs &b, const double2 *gT, const double2 *gE,
+                             void *out, hipStream_t s);
+hipError_t launch_ring_adj(const Shape &sh, const Bufs &b, const void *G, const void *G2, void *F,
+                           double *fpart, double fnl, hipStream_t s);
+hipError_t launch_filter_t(const Shape &sh, const Bufs &b, const void *phibar, void *gout,
+                           hipStream_t s);
+hipError_t launch_fbar(const Shape &sh, const Bufs &b, const double *fpart, const double2 *gT,
+                       const double2 *gE, double *out, hipStream_t s);
 hipError_t launch_phi_to_api(const Shape &sh, const void *phi, double2 *api, hipStream_t s);
 hipError_t launch_api_to_phi(const Shape &sh, const double2 *api, void *phi, hipStream_t s);
 

@@ -56,14 +56,15 @@ __device__ inline int l_of_index(long long idx) {
 // the noise row n[j][idx(l, 0) ..], so a complex coefficient is two real
 // columns and the real filter multiplies both.
 template <typename T>
-__global__ __launch_bounds__(256) void k_filter(Shape sh, const T *__restrict__ FT, int Kpad,
-                                                int Mpad, const int2 *__restrict__ tiles,
-                                                const T *__restrict__ noise, T *__restrict__ phi)
+__device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FT, int Kpad,
+                                            int Mpad, const int2 *__restrict__ tiles,
+                                            const T *__restrict__ noise, T *__restrict__ phi,
+                                            int bx, int by)
 {
     using M = Mt<T>;
-    const int2 tl = tiles[blockIdx.x];
+    const int2 tl = tiles[bx];
     const int l = tl.x, ct = tl.y;
-    const int row0 = blockIdx.y * 64;
+    const int row0 = by * 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wr = wave >> 1, wc = wave & 1;
     const int i16 = lane & 15, k4 = lane >> 4;
@@ -108,6 +109,14 @@ __global__ __launch_bounds__(256) void k_filter(Shape sh, const T *__restrict__ 
             }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter(Shape sh, const T *__restrict__ FT, int Kpad,
+                                                int Mpad, const int2 *__restrict__ tiles,
+                                                const T *__restrict__ noise, T *__restrict__ phi)
+{
+    body_filter<T>(sh, FT, Kpad, Mpad, tiles, noise, phi, blockIdx.x, blockIdx.y);
+}
+
 // ------------------------------------------------------- linear radial sum
 
 __device__ inline void neumaier(double &s, double &c, double v)
@@ -121,11 +130,11 @@ __device__ inline void neumaier(double &s, double &c, double v)
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__restrict__ V,
-                                                    const T *__restrict__ noise,
-                                                    double2 *__restrict__ aL)
+__device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *__restrict__ V,
+                                                const T *__restrict__ noise,
+                                                double2 *__restrict__ aL, int bid)
 {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long idx = (long long)bid * 256 + threadIdx.x;
     if (idx >= sh.nlm) return;
     const int l = l_of_index(idx);
     const bool m0 = lm_index(l, 0) == idx;
@@ -145,6 +154,14 @@ __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__re
     aL[sh.nlm + idx] = make_double2(s[2] + c[2], s[3] + c[3]);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__restrict__ V,
+                                                    const T *__restrict__ noise,
+                                                    double2 *__restrict__ aL)
+{
+    body_radial_lin<T>(sh, V, noise, aL, blockIdx.x);
+}
+
 // -------------------------------------------------------- Legendre synthesis
 
 // Block = (m, 64 ring pairs, column tile of 16 CF columns); wave w owns 16
@@ -153,15 +170,15 @@ __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__re
 // mod 16) and keeps the value its MFMA k-slot (lane / 16) needs; the
 // coefficient loads are wave-uniform.
 template <typename T, int CF>
-__global__ __launch_bounds__(256) void k_synth(Shape sh, const double *__restrict__ x,
-                                               const double *__restrict__ lmm,
-                                               const double2 *__restrict__ coef,
-                                               const T *__restrict__ phi, T *__restrict__ G)
+__device__ __forceinline__ void body_synth(const Shape &sh, const double *__restrict__ x,
+                                           const double *__restrict__ lmm,
+                                           const double2 *__restrict__ coef,
+                                           const T *__restrict__ phi, T *__restrict__ G, int bid)
 {
     using M = Mt<T>;
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int npt = (npair + kPairTile - 1) / kPairTile;
-    int b = blockIdx.x;
+    int b = bid;
     const int ct = b % sh.nct;
     b /= sh.nct;
     const int pt = b % npt;
@@ -216,6 +233,15 @@ __global__ __launch_bounds__(256) void k_synth(Shape sh, const double *__restric
                     G[(((long long)pair * (L + 1) + m) * 2 + par) * Cpad + colb + 16 * cf] =
                         acc[par][cf][r];
             }
+}
+
+template <typename T, int CF>
+__global__ __launch_bounds__(256) void k_synth(Shape sh, const double *__restrict__ x,
+                                               const double *__restrict__ lmm,
+                                               const double2 *__restrict__ coef,
+                                               const T *__restrict__ phi, T *__restrict__ G)
+{
+    body_synth<T, CF>(sh, x, lmm, coef, phi, G, blockIdx.x);
 }
 
 // ------------------------------------------------------------- ring FFTs
@@ -373,10 +399,10 @@ __device__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw)
 // of the square, n conj(G_L)^2, which is subtracted.  Blocks are numbered so
 // that consecutive shells of one pair run on the same XCD (shared L2 lines).
 template <typename T>
-__global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict__ wq,
-                                              const typename Mt<T>::c2 *__restrict__ tw,
-                                              const T *__restrict__ G, T *__restrict__ F,
-                                              double *__restrict__ maps, int mode)
+__device__ __forceinline__ void body_ring(const Shape &sh, const double *__restrict__ wq,
+                                          const typename Mt<T>::c2 *__restrict__ tw,
+                                          const T *__restrict__ G, T *__restrict__ F,
+                                          double *__restrict__ maps, int mode, int bid)
 {
     using C2 = typename Mt<T>::c2;
     extern __shared__ unsigned char smem_raw[];
@@ -384,7 +410,7 @@ __global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict
     const int L = sh.L, n = sh.nphi, Cpad = sh.Cpad;
     const int nblk = sh.npair * sh.N;
     const int nslot = (nblk + 7) / 8;
-    const int logical = (blockIdx.x & 7) * nslot + (blockIdx.x >> 3);
+    const int logical = (bid & 7) * nslot + (bid >> 3);
     if (logical >= nblk) return;
     const int s = logical % sh.N, p = logical / sh.N;
     const int tid = threadIdx.x;
@@ -464,6 +490,15 @@ __global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict__ wq,
+                                              const typename Mt<T>::c2 *__restrict__ tw,
+                                              const T *__restrict__ G, T *__restrict__ F,
+                                              double *__restrict__ maps, int mode)
+{
+    body_ring<T>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
+}
+
 // --------------------------------------------------------- Legendre analysis
 
 // Block = (m, 128 l rows, column tile).  Wave w owns rows l0w .. l0w+31,
@@ -473,21 +508,25 @@ __global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict
 // stages the 32 x 64 values in LDS and reads them back in the MFMA A layout
 // (lane = (row, pair)).  mode 0 folds the radial sum into the epilogue:
 // part[ct][X][idx(l, m)] = sum_s W^X_ls Phi_NL,lm(s) over the tile's shells.
+// mode 2 (reverse pass): per-shell output plus the direct cotangent
+// sum_X W^X_ls abar^X_lm, no mean handling.
 template <typename T, int CF, int MODE>
-__global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__ tiles,
-                                              const double *__restrict__ x,
-                                              const double2 *__restrict__ coef,
-                                              const double2 *__restrict__ seed,
-                                              const int *__restrict__ seedoff,
-                                              const double *__restrict__ W,
-                                              const double *__restrict__ mu,
-                                              const T *__restrict__ F, double2 *__restrict__ part,
-                                              T *__restrict__ outphi)
+__device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restrict__ tiles,
+                                          const double *__restrict__ x,
+                                          const double2 *__restrict__ coef,
+                                          const double2 *__restrict__ seed,
+                                          const int *__restrict__ seedoff,
+                                          const double *__restrict__ W,
+                                          const double *__restrict__ mu,
+                                          const T *__restrict__ F, double2 *__restrict__ part,
+                                          T *__restrict__ outphi,
+                                          const double2 *__restrict__ gT,
+                                          const double2 *__restrict__ gE, int bid)
 {
     using M = Mt<T>;
     __shared__ T lam[4][32][65];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
-    const int4 tl = tiles[blockIdx.x];
+    const int4 tl = tiles[bid];
     const int m = tl.x, lt = tl.y, ct = tl.z;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, k4 = lane >> 4;
@@ -555,6 +594,18 @@ __global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__
                 const int col = colb + 16 * cf;
                 const int s = col >> 1;
                 double v = (double)acc[par][cf][r];
+                if (MODE == 2) {
+                    if (lok) {
+                        const long long id = lm_index(l, m);
+                        const double2 t = gT[id], e = gE[id];
+                        const double wt = W[(long long)l * Npad + s];
+                        const double we = W[(long long)(L + 1 + l) * Npad + s];
+                        v += (col & 1) ? (m == 0 ? 0.0 : wt * t.y + we * e.y) : wt * t.x + we * e.x;
+                        if (m == 0 && (col & 1)) v = 0.0;
+                        outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
+                    }
+                    continue;
+                }
                 if (m == 0 && l == 0) {
                     if (sh.mean_mode == 0)
                         v = 0.0;
@@ -589,15 +640,32 @@ __global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__
         }
 }
 
+template <typename T, int CF, int MODE>
+__global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__ tiles,
+                                              const double *__restrict__ x,
+                                              const double2 *__restrict__ coef,
+                                              const double2 *__restrict__ seed,
+                                              const int *__restrict__ seedoff,
+                                              const double *__restrict__ W,
+                                              const double *__restrict__ mu,
+                                              const T *__restrict__ F, double2 *__restrict__ part,
+                                              T *__restrict__ outphi,
+                                              const double2 *__restrict__ gT,
+                                              const double2 *__restrict__ gE)
+{
+    body_anal<T, CF, MODE>(sh, tiles, x, coef, seed, seedoff, W, mu, F, part, outphi, gT, gE,
+                           blockIdx.x);
+}
+
 // -------------------------------------------------------------- combine
 
-__global__ __launch_bounds__(256) void k_combine(Shape sh, const double2 *__restrict__ part,
-                                                 const double2 *__restrict__ aL, double fnl,
-                                                 double2 *__restrict__ aT, double2 *__restrict__ aE,
-                                                 double2 *__restrict__ aTn,
-                                                 double2 *__restrict__ aEn)
+__device__ __forceinline__ void body_combine(const Shape &sh, const double2 *__restrict__ part,
+                                             const double2 *__restrict__ aL, double fnl,
+                                             double2 *__restrict__ aT, double2 *__restrict__ aE,
+                                             double2 *__restrict__ aTn, double2 *__restrict__ aEn,
+                                             int bid)
 {
-    const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long idx = (long long)bid * 256 + threadIdx.x;
     if (idx >= sh.nlm) return;
     const int l = l_of_index(idx);
     const bool m0 = lm_index(l, 0) == idx;
@@ -620,6 +688,112 @@ __global__ __launch_bounds__(256) void k_combine(Shape sh, const double2 *__rest
             if (aEn) aEn[idx] = nl;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_combine(Shape sh, const double2 *__restrict__ part,
+                                                 const double2 *__restrict__ aL, double fnl,
+                                                 double2 *__restrict__ aT, double2 *__restrict__ aE,
+                                                 double2 *__restrict__ aTn,
+                                                 double2 *__restrict__ aEn)
+{
+    body_combine(sh, part, aL, fnl, aT, aE, aTn, aEn, blockIdx.x);
+}
+
+// ----------------------------------------------------- grouped (batch) entry
+//
+// A batch of contexts runs each stage as one launch: block b belongs to the
+// context c with off[c] <= b < off[c+1] (offsets are multiples of 8, so the
+// XCD-aware numbering of the ring stage is kept per context) and runs that
+// context's block b - off[c].  Items carry each context's shape, buffers and
+// the per-call pointers.
+
+__device__ inline int group_find(const int *__restrict__ off, int n, int b, int &local)
+{
+    int lo = 0, hi = n;  // off[lo] <= b < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    local = b - off[lo];
+    return lo;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void g_radial_lin(const GroupItem *__restrict__ it,
+                                                    const int *__restrict__ ord,
+                                                    const int *__restrict__ off, int n)
+{
+    int lb;
+    const int k = group_find(off, n, blockIdx.x, lb);
+    const GroupItem &g = it[ord[k]];
+    if (lb >= (int)((g.sh.nlm + 255) / 256)) return;
+    body_radial_lin<T>(g.sh, g.b.V, (const T *)g.noise, g.b.aL, lb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void g_filter(const GroupItem *__restrict__ it,
+                                                const int *__restrict__ ord,
+                                                const int *__restrict__ off, int n)
+{
+    int lb;
+    const int k = group_find(off, n, blockIdx.x, lb);
+    const GroupItem &g = it[ord[k]];
+    const int nx = g.b.nk1;
+    if (lb >= nx * (g.b.Mpad / 64)) return;
+    body_filter<T>(g.sh, (const T *)g.b.FT, g.b.Kpad, g.b.Mpad, g.b.k1tiles, (const T *)g.noise,
+                   (T *)g.b.phi, lb % nx, lb / nx);
+}
+
+template <typename T, int CF>
+__global__ __launch_bounds__(256) void g_synth(const GroupItem *__restrict__ it,
+                                               const int *__restrict__ ord,
+                                               const int *__restrict__ off, int n)
+{
+    int lb;
+    const int k = group_find(off, n, blockIdx.x, lb);
+    const GroupItem &g = it[ord[k]];
+    const int npt = (g.sh.npair + kPairTile - 1) / kPairTile;
+    if (lb >= (g.sh.L + 1) * npt * g.sh.nct) return;
+    body_synth<T, CF>(g.sh, g.b.x, g.b.lmm, g.b.coef, (const T *)g.b.phi, (T *)g.b.G, lb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void g_ring(const GroupItem *__restrict__ it,
+                                              const int *__restrict__ ord,
+                                              const int *__restrict__ off, int n)
+{
+    int lb;
+    const int k = group_find(off, n, blockIdx.x, lb);
+    const GroupItem &g = it[ord[k]];
+    body_ring<T>(g.sh, g.b.wq, (const typename Mt<T>::c2 *)g.b.tw, (const T *)g.b.G, (T *)g.b.F,
+                 nullptr, 0, lb);
+}
+
+template <typename T, int CF>
+__global__ __launch_bounds__(256) void g_anal(const GroupItem *__restrict__ it,
+                                              const int *__restrict__ ord,
+                                              const int *__restrict__ off, int n)
+{
+    int lb;
+    const int k = group_find(off, n, blockIdx.x, lb);
+    const GroupItem &g = it[ord[k]];
+    if (lb >= g.b.nk4) return;
+    body_anal<T, CF, 0>(g.sh, g.b.k4tiles, g.b.x, g.b.coef, g.b.seed, g.b.seedoff, g.b.W, g.b.mu,
+                        (const T *)g.b.F, g.b.part, nullptr, nullptr, nullptr, lb);
+}
+
+__global__ __launch_bounds__(256) void g_combine(const GroupItem *__restrict__ it,
+                                                 const int *__restrict__ ord,
+                                                 const int *__restrict__ off, int n)
+{
+    int lb;
+    const int k = group_find(off, n, blockIdx.x, lb);
+    const GroupItem &g = it[ord[k]];
+    if (lb >= (int)((g.sh.nlm + 255) / 256)) return;
+    body_combine(g.sh, g.b.part, g.b.aL, g.fnl, g.aT, g.aE, nullptr, nullptr, lb);
 }
 
 // --------------------------------------------------------- recurrence seeds
@@ -685,6 +859,245 @@ __global__ __launch_bounds__(256) void k_api_to_phi(Shape sh, const double2 *__r
     const double2 v = api[t];
     dst[0] = (T)v.x;
     dst[1] = m == 0 ? T(0) : (T)v.y;
+}
+
+// ------------------------------------------------------------ reverse pass
+
+// Transposed radial sum, written as a synthesis input: for every (l, m) and
+// shell s, sum_X W^X_ls abar^X_lm.  The adjoint of the analysis sums every
+// stored (l, m >= 0) once, while the synthesis kernels weight m > 0 twice
+// (real field), so m > 0 is halved here.  For the sample mean the (0, 0)
+// entry is dropped: the derivative of the removed sky mean cancels it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_radial_adj(Shape sh, const double *__restrict__ W,
+                                                    const double2 *__restrict__ gT,
+                                                    const double2 *__restrict__ gE,
+                                                    T *__restrict__ out)
+{
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= sh.nlm * sh.C) return;
+    const int c = (int)(t % sh.C);
+    const long long idx = t / sh.C;
+    const int l = l_of_index(idx);
+    const int m = (int)(idx - lm_index(l, 0));
+    const int s = c >> 1;
+    const int Npad = sh.Cpad / 2;
+    const double wt = W[(long long)l * Npad + s];
+    const double we = W[(long long)(sh.L + 1 + l) * Npad + s];
+    const double2 a = gT[idx], e = gE[idx];
+    double v = (c & 1) ? wt * a.y + we * e.y : wt * a.x + we * e.x;
+    if (m == 0 && (c & 1)) v = 0.0;
+    if (m > 0) v *= 0.5;
+    if (m == 0 && l == 0 && sh.mean_mode == 0) v = 0.0;
+    out[mrow(sh.L, m, l) * sh.Cpad + c] = (T)v;
+}
+
+// Reverse ring stage, block = (ring pair, shell).  Both the Phi_L map (from
+// G) and the transposed-analysis map ghat (from G2, pixel weights applied
+// here) are rebuilt by inverse FFTs; phibar = 2 f_NL Phi_L ghat is formed
+// pixel by pixel together with this block's share of dLoss/df_NL =
+// sum_pix Phi_L^2 ghat, and phibar goes through the forward FFT.  The
+// transposed synthesis needs c_m sum_pix phibar e^{-i m phi}; with n = 3L the
+// bin L also holds mode -2L of phibar, 2 f_NL w conj(G_L) conj(G2_L) n, which
+// is removed.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__restrict__ wq,
+                                                  const typename Mt<T>::c2 *__restrict__ tw,
+                                                  const T *__restrict__ G,
+                                                  const T *__restrict__ G2, T *__restrict__ F,
+                                                  double *__restrict__ fpart, double fnl)
+{
+    using C2 = typename Mt<T>::c2;
+    extern __shared__ unsigned char smem_raw[];
+    const int L = sh.L, n = sh.nphi, Cpad = sh.Cpad;
+    C2 *b1 = reinterpret_cast<C2 *>(smem_raw);
+    C2 *b2 = b1 + n;
+    __shared__ double red[256];
+    const int nblk = sh.npair * sh.N;
+    const int nslot = (nblk + 7) / 8;
+    const int logical = (blockIdx.x & 7) * nslot + (blockIdx.x >> 3);
+    if (logical >= nblk) return;
+    const int s = logical % sh.N, p = logical / sh.N;
+    const int tid = threadIdx.x;
+    const bool eq = sh.equator && p == sh.npair - 1;
+
+    for (int q = tid; q < n; q += 256) {
+        C2 z;
+        z.x = T(0);
+        z.y = T(0);
+        b1[q] = z;
+        b2[q] = z;
+    }
+    __syncthreads();
+    const long long poff = (long long)p * (L + 1) * 2 * Cpad + 2 * s;
+    for (int m = tid; m <= L; m += 256) {
+#pragma unroll
+        for (int which = 0; which < 2; which++) {
+            const T *g = (which ? G2 : G) + poff + (long long)m * 2 * Cpad;
+            const T Er = g[0], Ei = g[1], Or = g[Cpad], Oi = g[Cpad + 1];
+            T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
+            if (eq) Sr = Si = T(0);
+            if (m == 0) Ni = Si = T(0);
+            C2 *bb = which ? b2 : b1;
+            C2 z;
+            z.x = Nr - Si;
+            z.y = Ni + Sr;
+            bb[m] = z;
+            if (m > 0) {
+                z.x = Nr + Si;
+                z.y = Sr - Ni;
+                bb[n - m] = z;
+            }
+        }
+    }
+    __syncthreads();
+    fft_lds<C2, true>(b1, sh, tw);
+    fft_lds<C2, true>(b2, sh, tw);
+    const T wpix = (T)wq[p];
+    const T two_f = (T)(2.0 * fnl);
+    double fb = 0.0;
+    for (int j = tid; j < n; j += 256) {
+        const C2 f = b1[j];
+        C2 g = b2[j];
+        g.x *= wpix;
+        g.y *= wpix;
+        fb += (double)f.x * (double)f.x * (double)g.x;
+        if (!eq) fb += (double)f.y * (double)f.y * (double)g.y;
+        C2 ph;
+        ph.x = two_f * f.x * g.x;
+        ph.y = eq ? T(0) : two_f * f.y * g.y;
+        b1[j] = ph;
+    }
+    red[tid] = fb;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) fpart[(long long)p * sh.N + s] = red[0];
+    fft_lds<C2, false>(b1, sh, tw);
+    const T half = T(0.5);
+    for (int m = tid; m <= L; m += 256) {
+        const C2 W1 = b1[m];
+        const C2 W2 = b1[m == 0 ? 0 : n - m];
+        T Ar = half * (W1.x + W2.x), Ai = half * (W1.y - W2.y);
+        T Br = half * (W1.y + W2.y), Bi = -half * (W1.x - W2.x);
+        if (sh.alias && m == L) {
+            const T *g = G + poff + (long long)L * 2 * Cpad;
+            const T *h = G2 + poff + (long long)L * 2 * Cpad;
+            T Nr = g[0] + g[Cpad], Ni = g[1] + g[Cpad + 1];
+            T Sr = g[0] - g[Cpad], Si = g[1] - g[Cpad + 1];
+            T Mr = h[0] + h[Cpad], Mi = h[1] + h[Cpad + 1];
+            T Rr = h[0] - h[Cpad], Ri = h[1] - h[Cpad + 1];
+            if (eq) Sr = Si = Rr = Ri = T(0);
+            const T k = (T)n * two_f * wpix;
+            // conj(N) conj(M) = (Nr Mr - Ni Mi, -(Nr Mi + Ni Mr))
+            Ar -= k * (Nr * Mr - Ni * Mi);
+            Ai -= k * (-(Nr * Mi + Ni * Mr));
+            Br -= k * (Sr * Rr - Si * Ri);
+            Bi -= k * (-(Sr * Ri + Si * Rr));
+        }
+        if (eq) Br = Bi = T(0);
+        const T cm = m == 0 ? T(1) : T(2);
+        T FEr = cm * (Ar + Br), FEi = cm * (Ai + Bi);
+        T FOr = cm * (Ar - Br), FOi = cm * (Ai - Bi);
+        if (eq) FOr = FOi = T(0);
+        if (m == 0) FEi = FOi = T(0);
+        T *f = F + ((long long)m * sh.npair + p) * 2 * Cpad + 2 * s;
+        f[0] = FEr;
+        f[1] = FEi;
+        f[Cpad] = FOr;
+        f[Cpad + 1] = FOi;
+    }
+}
+
+// Transposed filter: nbar_j = sum_i F_l,ij Phibar_L,i for every l, written in
+// the noise layout [N][n_lm] complex.  Same tiling as k_filter with the roles
+// of the two shell indices exchanged (A[j][i] = F_l[i][j]).
+template <typename T>
+__global__ __launch_bounds__(256) void k_filter_t(Shape sh, const T *__restrict__ FT, int Kpad,
+                                                  int Mpad, const int2 *__restrict__ tiles,
+                                                  const T *__restrict__ phibar,
+                                                  T *__restrict__ gout)
+{
+    using M = Mt<T>;
+    const int2 tl = tiles[blockIdx.x];
+    const int l = tl.x, ct = tl.y;
+    const int row0 = blockIdx.y * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave >> 1, wc = wave & 1;
+    const int i16 = lane & 15, k4 = lane >> 4;
+    const int ncol = 2 * (l + 1);
+    const long long nlm = sh.nlm;
+    const T *FTl = FT + (long long)l * Kpad * Mpad;
+    typename M::acc acc[2][2];
+    for (int a = 0; a < 2; a++)
+        for (int c = 0; c < 2; c++) acc[a][c] = typename M::acc{};
+    const int rowA = row0 + 32 * wr + i16;
+    const int colB = ct * 64 + 32 * wc + i16;
+    for (int i0 = 0; i0 < Kpad; i0 += 4) {
+        const int i = i0 + k4;
+        T av[2], bv[2];
+#pragma unroll
+        for (int ri = 0; ri < 2; ri++) {
+            const int j = rowA + 16 * ri;
+            av[ri] = j < sh.N ? FTl[(long long)j * Mpad + i] : T(0);
+        }
+#pragma unroll
+        for (int ci = 0; ci < 2; ci++) {
+            const int col = colB + 16 * ci;
+            bv[ci] = (i < sh.N && col < ncol)
+                         ? phibar[mrow(sh.L, col >> 1, l) * sh.Cpad + 2 * i + (col & 1)]
+                         : T(0);
+        }
+#pragma unroll
+        for (int ri = 0; ri < 2; ri++)
+#pragma unroll
+            for (int ci = 0; ci < 2; ci++) acc[ri][ci] = M::mfma(av[ri], bv[ci], acc[ri][ci]);
+    }
+#pragma unroll
+    for (int ri = 0; ri < 2; ri++)
+#pragma unroll
+        for (int ci = 0; ci < 2; ci++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int j = row0 + 32 * wr + 16 * ri + M::row(k4, r);
+                const int col = colB + 16 * ci;
+                if (j < sh.N && col < ncol) {
+                    const int m = col >> 1;
+                    const bool zero = m == 0 && (col & 1);
+                    gout[((long long)j * nlm + lm_index(l, m)) * 2 + (col & 1)] =
+                        zero ? T(0) : (T)acc[ri][ci][r];
+                }
+            }
+}
+
+// dLoss/df_NL = sum over ring blocks (fixed order), minus the ensemble-mean
+// term sum_s sqrt(4 pi) <Phi_L^2>(r_s) Re(sum_X W^X_0s abar^X_00).
+__global__ __launch_bounds__(256) void k_fbar(Shape sh, const double *__restrict__ fpart,
+                                              const double *__restrict__ W,
+                                              const double *__restrict__ mu,
+                                              const double2 *__restrict__ gT,
+                                              const double2 *__restrict__ gE,
+                                              double *__restrict__ out)
+{
+    __shared__ double red[256];
+    const int tid = threadIdx.x;
+    const long long n = (long long)sh.npair * sh.N;
+    double acc = 0.0;
+    for (long long q = tid; q < n; q += 256) acc += fpart[q];
+    if (sh.mean_mode == 1) {
+        const int Npad = sh.Cpad / 2;
+        for (int s = tid; s < sh.N; s += 256)
+            acc -= mu[s] * (W[s] * gT[0].x + W[(long long)(sh.L + 1) * Npad + s] * gE[0].x);
+    }
+    red[tid] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) *out = red[0];
 }
 
 // ------------------------------------------------------------- launchers
@@ -781,37 +1194,40 @@ hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F
 
 template <typename T, int CF>
 static void anal_t(const Shape &sh, const Bufs &b, const void *F, void *out, int mode,
-                   hipStream_t s)
+                   const double2 *gT, const double2 *gE, hipStream_t s)
 {
     dim3 grid(b.nk4);
     if (mode == 0)
         hipLaunchKernelGGL((k_anal<T, CF, 0>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
-                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out);
-    else
+                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out, gT, gE);
+    else if (mode == 1)
         hipLaunchKernelGGL((k_anal<T, CF, 1>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
-                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out);
+                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out, gT, gE);
+    else
+        hipLaunchKernelGGL((k_anal<T, CF, 2>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
+                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out, gT, gE);
 }
 
 template <typename T>
 static void anal_cf(const Shape &sh, const Bufs &b, const void *F, void *out, int mode,
-                    hipStream_t s)
+                    const double2 *gT, const double2 *gE, hipStream_t s)
 {
     switch (sh.CF) {
-    case 1: anal_t<T, 1>(sh, b, F, out, mode, s); break;
-    case 2: anal_t<T, 2>(sh, b, F, out, mode, s); break;
-    case 3: anal_t<T, 3>(sh, b, F, out, mode, s); break;
-    case 4: anal_t<T, 4>(sh, b, F, out, mode, s); break;
-    default: anal_t<T, 5>(sh, b, F, out, mode, s); break;
+    case 1: anal_t<T, 1>(sh, b, F, out, mode, gT, gE, s); break;
+    case 2: anal_t<T, 2>(sh, b, F, out, mode, gT, gE, s); break;
+    case 3: anal_t<T, 3>(sh, b, F, out, mode, gT, gE, s); break;
+    case 4: anal_t<T, 4>(sh, b, F, out, mode, gT, gE, s); break;
+    default: anal_t<T, 5>(sh, b, F, out, mode, gT, gE, s); break;
     }
 }
 
 hipError_t launch_anal(const Shape &sh, const Bufs &b, const void *F_in, void *out_phi, int mode,
-                       hipStream_t s)
+                       hipStream_t s, const double2 *gT, const double2 *gE)
 {
     if (sh.fp32)
-        anal_cf<float>(sh, b, F_in, out_phi, mode, s);
+        anal_cf<float>(sh, b, F_in, out_phi, mode, gT, gE, s);
     else
-        anal_cf<double>(sh, b, F_in, out_phi, mode, s);
+        anal_cf<double>(sh, b, F_in, out_phi, mode, gT, gE, s);
     return hipGetLastError();
 }
 
@@ -842,6 +1258,132 @@ hipError_t launch_api_to_phi(const Shape &sh, const double2 *api, void *phi, hip
     else
         hipLaunchKernelGGL(k_api_to_phi<double>, grid, dim3(256), 0, s, sh, api, (double *)phi);
     return hipGetLastError();
+}
+
+hipError_t launch_radial_adj(const Shape &sh, const Bufs &b, const double2 *gT, const double2 *gE,
+                             void *out, hipStream_t s)
+{
+    dim3 grid(blocks_for(sh.nlm * sh.C, 256));
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_radial_adj<float>, grid, dim3(256), 0, s, sh, b.W, gT, gE, (float *)out);
+    else
+        hipLaunchKernelGGL(k_radial_adj<double>, grid, dim3(256), 0, s, sh, b.W, gT, gE,
+                           (double *)out);
+    return hipGetLastError();
+}
+
+hipError_t launch_ring_adj(const Shape &sh, const Bufs &b, const void *G, const void *G2, void *F,
+                           double *fpart, double fnl, hipStream_t s)
+{
+    const long long nblk = (long long)sh.npair * sh.N;
+    dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
+    if (sh.fp32) {
+        const size_t lds = 2 * sizeof(float2) * sh.nphi;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_ring_adj<float>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_ring_adj<float>, grid, dim3(256), lds, s, sh, b.wq,
+                           (const float2 *)b.tw, (const float *)G, (const float *)G2, (float *)F,
+                           fpart, fnl);
+    } else {
+        const size_t lds = 2 * sizeof(double2) * sh.nphi;
+        if (lds > 65536)
+            (void)hipFuncSetAttribute((const void *)k_ring_adj<double>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_ring_adj<double>, grid, dim3(256), lds, s, sh, b.wq,
+                           (const double2 *)b.tw, (const double *)G, (const double *)G2,
+                           (double *)F, fpart, fnl);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_filter_t(const Shape &sh, const Bufs &b, const void *phibar, void *gout,
+                           hipStream_t s)
+{
+    dim3 grid(b.nk1, b.Mpad / 64);
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_filter_t<float>, grid, dim3(256), 0, s, sh, (const float *)b.FT,
+                           b.Kpad, b.Mpad, b.k1tiles, (const float *)phibar, (float *)gout);
+    else
+        hipLaunchKernelGGL(k_filter_t<double>, grid, dim3(256), 0, s, sh, (const double *)b.FT,
+                           b.Kpad, b.Mpad, b.k1tiles, (const double *)phibar, (double *)gout);
+    return hipGetLastError();
+}
+
+hipError_t launch_fbar(const Shape &sh, const Bufs &b, const double *fpart, const double2 *gT,
+                       const double2 *gE, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fbar, dim3(1), dim3(256), 0, s, sh, fpart, b.W, b.mu, gT, gE, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ grouped launches
+
+long long group_blocks(int stage, const Shape &sh, const Bufs &b)
+{
+    switch (stage) {
+    case GS_RADIAL_LIN:
+    case GS_COMBINE: return (sh.nlm + 255) / 256;
+    case GS_FILTER: return (long long)b.nk1 * (b.Mpad / 64);
+    case GS_SYNTH: return (long long)(sh.L + 1) * ((sh.npair + kPairTile - 1) / kPairTile) * sh.nct;
+    case GS_RING: return ((long long)sh.npair * sh.N + 7) / 8 * 8;
+    case GS_ANAL: return b.nk4;
+    default: return 0;
+    }
+}
+
+template <typename T, int CF>
+static void group_cf(int stage, const GroupItem *it, const int *ord, const int *off, int n,
+                     dim3 grid, hipStream_t s)
+{
+    if (stage == GS_SYNTH)
+        hipLaunchKernelGGL((g_synth<T, CF>), grid, dim3(256), 0, s, it, ord, off, n);
+    else
+        hipLaunchKernelGGL((g_anal<T, CF>), grid, dim3(256), 0, s, it, ord, off, n);
+}
+
+template <typename T>
+static void group_t(int stage, int CF, const GroupItem *it, const int *ord, const int *off, int n,
+                    dim3 grid, size_t lds, hipStream_t s)
+{
+    switch (stage) {
+    case GS_RADIAL_LIN:
+        hipLaunchKernelGGL(g_radial_lin<T>, grid, dim3(256), 0, s, it, ord, off, n);
+        break;
+    case GS_FILTER: hipLaunchKernelGGL(g_filter<T>, grid, dim3(256), 0, s, it, ord, off, n); break;
+    case GS_RING: hipLaunchKernelGGL(g_ring<T>, grid, dim3(256), lds, s, it, ord, off, n); break;
+    case GS_COMBINE: hipLaunchKernelGGL(g_combine, grid, dim3(256), 0, s, it, ord, off, n); break;
+    default:
+        switch (CF) {
+        case 1: group_cf<T, 1>(stage, it, ord, off, n, grid, s); break;
+        case 2: group_cf<T, 2>(stage, it, ord, off, n, grid, s); break;
+        case 3: group_cf<T, 3>(stage, it, ord, off, n, grid, s); break;
+        case 4: group_cf<T, 4>(stage, it, ord, off, n, grid, s); break;
+        default: group_cf<T, 5>(stage, it, ord, off, n, grid, s); break;
+        }
+    }
+}
+
+hipError_t launch_group(int stage, int fp32, int CF, const GroupItem *items, const int *ord,
+                        const int *off, int n, int nblocks, size_t lds, hipStream_t s)
+{
+    if (nblocks <= 0) return hipSuccess;
+    dim3 grid((unsigned)nblocks);
+    if (fp32)
+        group_t<float>(stage, CF, items, ord, off, n, grid, lds, s);
+    else
+        group_t<double>(stage, CF, items, ord, off, n, grid, lds, s);
+    return hipGetLastError();
+}
+
+hipError_t prepare_group_ring(int fp32, size_t lds)
+{
+    if (lds <= 65536) return hipSuccess;
+    if (fp32)
+        return hipFuncSetAttribute((const void *)g_ring<float>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipFuncSetAttribute((const void *)g_ring<double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 }  // namespace fnl

@@ -94,10 +94,11 @@ def sph_bessel_table(L, x):
     """j_l(x) for l = 0..L at every x > 0 (1-D), shape [L+1, x.size].
 
     For x > L + 60 the upward recurrence from j_0, j_1 is stable over l <= L.
-    Otherwise Miller's downward recurrence from l = L + 200 is used, with
-    rescaling against overflow and normalisation by the identity
-    sum_l (2l+1) j_l(x)^2 = 1; the sign is taken from whichever of j_0, j_1
-    is larger in magnitude.
+    Otherwise Miller's downward recurrence is used, started at
+    l = max(x) + 60 + 8 max(x)^(1/3) (beyond which j_l is below 1e-30 of its
+    peak) but not above L + 200, with rescaling against overflow and
+    normalisation by the identity sum_l (2l+1) j_l(x)^2 = 1; the sign is taken
+    from whichever of j_0, j_1 is larger in magnitude.
     """
     x = np.asarray(x, dtype=np.float64).ravel()
     out = np.zeros((L + 1, x.size))
@@ -118,7 +119,9 @@ def sph_bessel_table(L, x):
     if np.any(dn):
         xs = x[dn]
         Ls = max(L, 1)                      # keep j_1 for the sign test
-        top = Ls + 200
+        xmax = float(np.max(xs))
+        top = int(min(Ls + 200, xmax + 60 + 8 * xmax ** (1 / 3)))
+        top = max(top, 2)
         t_next = np.zeros_like(xs)          # t_{l+1}
         t_cur = np.full_like(xs, 1e-100)    # t_l at l = top
         scale = np.zeros(xs.size, dtype=np.int64)
