@@ -174,6 +174,35 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
     }
 }
 
+// Lay out groups of blocks for the 8 XCDs: groups are assigned greedily in
+// order of decreasing work to the least loaded XCD (each XCD then runs its
+// groups heaviest first, the blocks of a group back to back so they share that
+// XCD's L2), and block b of the launch is entry b / 8 of XCD b % 8's list.
+// Shorter lists are padded with idle entries (m = -1).
+std::vector<int4> xcd_layout(const std::vector<std::vector<int4>> &groups,
+                             const std::vector<double> &work)
+{
+    constexpr int kXcd = 8;
+    std::vector<int> order(groups.size());
+    for (size_t i = 0; i < order.size(); i++) order[i] = (int)i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    std::vector<std::vector<int4>> lists(kXcd);
+    std::vector<double> load(kXcd, 0.0);
+    for (int g : order) {
+        int best = 0;
+        for (int x = 1; x < kXcd; x++)
+            if (load[x] < load[best]) best = x;
+        load[best] += work[g] * (double)groups[g].size();
+        lists[best].insert(lists[best].end(), groups[g].begin(), groups[g].end());
+    }
+    size_t len = 0;
+    for (auto &l : lists) len = std::max(len, l.size());
+    std::vector<int4> out(len * kXcd, make_int4(-1, 0, 0, 0));
+    for (int x = 0; x < kXcd; x++)
+        for (size_t i = 0; i < lists[x].size(); i++) out[i * kXcd + x] = lists[x][i];
+    return out;
+}
+
 // lambda_mm(x) = (-1)^m sqrt((2m+1)!!/(4 pi (2m)!!)) (1-x^2)^{m/2}, built as a
 // product with the exponent kept apart (frexp) so that no intermediate
 // underflows; values below 1e-300 are flushed to 0 (their whole column of
@@ -332,6 +361,14 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     sh.nlm = (long long)(L + 1) * (L + 2) / 2;
     sh.mean_mode = o.mean_mode;
     sh.fp32 = o.precision == SIM_FP32;
+    sh.lower = 1;
+    for (int l = 0; l <= L && sh.lower; l++)
+        for (int i = 0; i < N && sh.lower; i++)
+            for (int j = i + 1; j < N; j++)
+                if (filter[((size_t)l * N + i) * N + j] != 0.0) {
+                    sh.lower = 0;
+                    break;
+                }
 
     sim_ctx *c = new (std::nothrow) sim_ctx();
     if (!c) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
@@ -403,10 +440,29 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     for (int l = 0; l <= L; l++)
         for (int ct = 0; ct < (2 * (l + 1) + 63) / 64; ct++) k1.push_back(make_int2(l, ct));
     b.nk1 = (int)k1.size();
-    std::vector<int4> k4;
-    for (int m = 0; m <= L; m++)
-        for (int lt = 0; lt < (L - m + 1 + fnl::kLTile - 1) / fnl::kLTile; lt++)
-            for (int ct = 0; ct < sh.nct; ct++) k4.push_back(make_int4(m, lt, ct, 0));
+    // synthesis: a group is the pair tiles of one (m, column tile), which read
+    // the same Phi_m columns; analysis: the l tiles of one (m, column tile),
+    // which read the same F_m columns
+    std::vector<int4> k2, k4;
+    {
+        const int npt = (np + fnl::kPairTile - 1) / fnl::kPairTile;
+        std::vector<std::vector<int4>> g2, g4;
+        std::vector<double> w2, w4;
+        for (int m = 0; m <= L; m++)
+            for (int ct = 0; ct < sh.nct; ct++) {
+                std::vector<int4> a, c4;
+                for (int pt = 0; pt < npt; pt++) a.push_back(make_int4(m, pt, ct, 0));
+                for (int lt = 0; lt < (L - m + 1 + fnl::kLTile - 1) / fnl::kLTile; lt++)
+                    c4.push_back(make_int4(m, lt, ct, 0));
+                g2.push_back(a);
+                w2.push_back((double)(L - m + 1));
+                g4.push_back(c4);
+                w4.push_back(1.0);
+            }
+        k2 = xcd_layout(g2, w2);
+        k4 = xcd_layout(g4, w4);
+    }
+    b.nk2 = (int)k2.size();
     b.nk4 = (int)k4.size();
     b.Kpad = (N + 3) / 4 * 4;
     b.Mpad = (N + 63) / 64 * 64;
@@ -437,12 +493,17 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     UP(b.mu, mu);
     UP(b.seedoff, seedoff);
     UP(b.k1tiles, k1);
+    UP(b.k2tiles, k2);
     UP(b.k4tiles, k4);
 #undef UP
     {
         void *p = nullptr;
         if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)b.nseedrow * np))) goto bad;
         b.seed = (double2 *)p;
+        if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * np))) goto bad;
+        b.lstart = (int *)p;
+        if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 63) / 64)))) goto bad;
+        b.cmin = (int *)p;
         if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)sh.nct * 2 * sh.nlm))) goto bad;
         b.part = (double2 *)p;
         if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)2 * sh.nlm))) goto bad;

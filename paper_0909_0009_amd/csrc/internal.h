@@ -13,6 +13,7 @@ constexpr int kMaxPasses = 16;
 constexpr int kPairTile = 64;   // ring pairs per synthesis workgroup
 constexpr int kLTile = 128;     // l rows per analysis workgroup (4 waves x 32)
 constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
+constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)
 
 // Everything a kernel needs to know about the problem's shape.
 struct Shape {
@@ -33,6 +34,7 @@ struct Shape {
     long long nlm;
     int mean_mode;
     int fp32;     // 0: FP64 path, 1: FP32 matrix cores
+    int lower;    // 1 if every F_l is lower triangular (contractions stop at the diagonal)
 };
 
 // Row of coefficient (l, m) in the m-major layouts: rows of one m are
@@ -54,11 +56,16 @@ struct Bufs {
     double *wq;        // [npair] omega_p * 2 pi / nphi
     double *lmm;       // [L+1][npair] lambda_mm(x_p)
     double2 *coef;     // [nlm] (A, B): lambda_l = A x lambda_{l-1} - B lambda_{l-2}
-    double2 *seed;     // [nseedrow][npair] (lambda_l0, lambda_l0+1), l0 = m + 32u
+    double2 *seed;     // [nseedrow][npair] recurrence state (lambda_{l0-1}, lambda_{l0-2})
+                       // entering l0 = m + 32u ((0, lambda_mm) for u = 0)
     int *seedoff;      // [L+2] first seed row of each m
+    int *lstart;       // [L+1][npair] first l with |lambda_lm(x_p)| > 1e-30 (L+1 if none)
+    int *cmin;         // [L+1][ceil(npair/64)] min of lstart over each 64-pair chunk
     int2 *k1tiles;     // [nk1] (l, column tile) of each filter workgroup
-    int2 *k2tiles;     // unused placeholder
-    int4 *k4tiles;     // [nk4] (m, l tile, column tile, 0)
+    int4 *k2tiles;     // [nk2] synthesis blocks (m, pair tile, column tile, 0)
+    int4 *k4tiles;     // [nk4] analysis blocks (m, l tile, column tile, 0)
+                       // Both tables are in XCD order: block b runs entry b of the
+                       // table and is dispatched to XCD b % 8; m < 0 marks an idle block.
     void *tw;          // [nphi] e^{-2 pi i q / nphi}
     double *mu;        // [Cpad/2] sqrt(4 pi) * ensemble <Phi_L^2>(r_s)
     void *phi;         // [nlm rows][Cpad] Phi_L (m-major)
@@ -72,7 +79,7 @@ struct Bufs {
     double *fbar;      // reverse pass: [fbar_cap] dLoss/df_NL per realization (lazy)
     int fbar_cap;
     int Kpad, Mpad;
-    int nk1, nk4;
+    int nk1, nk2, nk4;
     long long nseedrow;
 };
 
@@ -101,7 +108,7 @@ hipError_t launch_group(int stage, int fp32, int CF, const GroupItem *items, con
 hipError_t prepare_group_ring(int fp32, size_t lds);
 
 // ----- launchers (kernels.hip); all asynchronous on `s`.
-hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);
+hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);  // seeds, lstart, cmin
 hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
                          hipStream_t s);
 hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);

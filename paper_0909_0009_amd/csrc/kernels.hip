@@ -77,7 +77,9 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
         for (int c = 0; c < 2; c++) acc[a][c] = typename M::acc{};
     const int rowA = row0 + 32 * wr + i16;
     const int colB = ct * 64 + 32 * wc + i16;
-    for (int j0 = 0; j0 < Kpad; j0 += 4) {
+    // lower-triangular F: rows < row0 + 64 need columns j < row0 + 64 only
+    const int jend = sh.lower ? min(Kpad, row0 + 64) : Kpad;
+    for (int j0 = 0; j0 < jend; j0 += 4) {
         const int j = j0 + k4;
         T av[2], bv[2];
 #pragma unroll
@@ -170,25 +172,36 @@ __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__re
 // mod 16) and keeps the value its MFMA k-slot (lane / 16) needs; the
 // coefficient loads are wave-uniform.
 template <typename T, int CF>
-__device__ __forceinline__ void body_synth(const Shape &sh, const double *__restrict__ x,
-                                           const double *__restrict__ lmm,
+__device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restrict__ tiles,
+                                           const double *__restrict__ x,
+                                           const double2 *__restrict__ seed,
+                                           const int *__restrict__ seedoff,
+                                           const int *__restrict__ lstart,
                                            const double2 *__restrict__ coef,
                                            const T *__restrict__ phi, T *__restrict__ G, int bid)
 {
     using M = Mt<T>;
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
-    const int npt = (npair + kPairTile - 1) / kPairTile;
-    int b = bid;
-    const int ct = b % sh.nct;
-    b /= sh.nct;
-    const int pt = b % npt;
-    const int m = b / npt;
+    const int4 tl = tiles[bid];
+    if (tl.x < 0) return;  // idle slot of the XCD layout
+    const int m = tl.x, pt = tl.y, ct = tl.z;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int p = pt * kPairTile + wave * 16 + i16;
     const bool pv = p < npair;
     const double xp = pv ? x[p] : 0.0;
-    double l1 = 0.0, l2 = pv ? lmm[(long long)m * npair + p] : 0.0;
+    // polar skip: start at the seed row below the first l where any of the
+    // wave's 16 pairs has |lambda_lm| > 1e-30 (wave-uniform)
+    int ls = pv ? lstart[(long long)m * npair + p] : L + 1;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) ls = min(ls, __shfl_xor(ls, o));
+    const int u0 = ls <= L ? (ls - m) / kSeedStride : 0;
+    double l1 = 0.0, l2 = 0.0;
+    if (pv && ls <= L) {
+        const double2 st = seed[((long long)seedoff[m] + u0) * npair + p];
+        l1 = st.x;
+        l2 = st.y;
+    }
     typename M::acc acc[2][CF];
 #pragma unroll
     for (int a = 0; a < 2; a++)
@@ -196,7 +209,24 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const double *__rest
         for (int c = 0; c < CF; c++) acc[a][c] = typename M::acc{};
     const long long rowm = mrow(L, m, m);
     const int colb = ct * sh.CT + i16;
-    for (int l0 = m; l0 <= L; l0 += 8) {
+    const int lbeg = ls <= L ? m + u0 * kSeedStride : L + 1;
+    // B operands of a K-step: rows l0 + 2 k4 (even l - m) and l0 + 2 k4 + 1 (odd),
+    // loaded one step ahead so the loads overlap the recurrence and the MFMAs
+    const T *colbase = phi + rowm * Cpad + colb;
+    T bE[CF], bO[CF];
+    auto loadB = [&](int l0, T *E, T *O) {
+        const int lE = l0 + 2 * k4;
+        const T *rE = colbase + (long long)(lE - m) * Cpad;
+#pragma unroll
+        for (int cf = 0; cf < CF; cf++) {
+            E[cf] = lE <= L ? rE[16 * cf] : T(0);
+            O[cf] = lE + 1 <= L ? rE[Cpad + 16 * cf] : T(0);
+        }
+    };
+    if (lbeg <= L) loadB(lbeg, bE, bO);
+    for (int l0 = lbeg; l0 <= L; l0 += 8) {
+        T nE[CF], nO[CF];
+        if (l0 + 8 <= L) loadB(l0 + 8, nE, nO);
         double v[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -209,17 +239,16 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const double *__rest
         }
         const double e = k4 == 0 ? v[0] : k4 == 1 ? v[2] : k4 == 2 ? v[4] : v[6];
         const double o = k4 == 0 ? v[1] : k4 == 1 ? v[3] : k4 == 2 ? v[5] : v[7];
-        const int lE = l0 + 2 * k4, lO = lE + 1;
         const T ae = (T)e, ao = (T)o;
-        const T *rE = phi + (rowm + (lE - m)) * Cpad;
-        const T *rO = rE + Cpad;
 #pragma unroll
         for (int cf = 0; cf < CF; cf++) {
-            const int col = colb + 16 * cf;
-            const T bE = (lE <= L) ? rE[col] : T(0);
-            const T bO = (lO <= L) ? rO[col] : T(0);
-            acc[0][cf] = M::mfma(ae, bE, acc[0][cf]);
-            acc[1][cf] = M::mfma(ao, bO, acc[1][cf]);
+            acc[0][cf] = M::mfma(ae, bE[cf], acc[0][cf]);
+            acc[1][cf] = M::mfma(ao, bO[cf], acc[1][cf]);
+        }
+#pragma unroll
+        for (int cf = 0; cf < CF; cf++) {
+            bE[cf] = nE[cf];
+            bO[cf] = nO[cf];
         }
     }
 #pragma unroll
@@ -236,12 +265,15 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const double *__rest
 }
 
 template <typename T, int CF>
-__global__ __launch_bounds__(256) void k_synth(Shape sh, const double *__restrict__ x,
-                                               const double *__restrict__ lmm,
+__global__ __launch_bounds__(256) void k_synth(Shape sh, const int4 *__restrict__ tiles,
+                                               const double *__restrict__ x,
+                                               const double2 *__restrict__ seed,
+                                               const int *__restrict__ seedoff,
+                                               const int *__restrict__ lstart,
                                                const double2 *__restrict__ coef,
                                                const T *__restrict__ phi, T *__restrict__ G)
 {
-    body_synth<T, CF>(sh, x, lmm, coef, phi, G, blockIdx.x);
+    body_synth<T, CF>(sh, tiles, x, seed, seedoff, lstart, coef, phi, G, blockIdx.x);
 }
 
 // ------------------------------------------------------------- ring FFTs
@@ -332,10 +364,10 @@ template <typename C2, int R, bool INV> __device__ inline void dft_small(C2 *a)
 // Butterfly i (k = i mod p) reads x_t = buf[i + t n/R], twists it by
 // w^{t k n/(p R)} and writes DFT_R(x)_t to buf[(i - k) R + k + t p].  All reads
 // finish before any write, so the pass works in place.
-template <typename C2, int R, bool INV>
+template <typename C2, int R, bool INV, int NMAX>
 __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
 {
-    constexpr int MAXB = (kMaxPhi / R + 255) / 256;
+    constexpr int MAXB = (NMAX / R + 255) / 256;
     const int nb = n / R;
     const int tstep = n / (p * R);
     C2 y[MAXB][R];
@@ -372,20 +404,22 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
     __syncthreads();
 }
 
-template <typename C2, bool INV>
+// NMAX: longest ring this instantiation handles (registers are reserved for
+// NMAX / 256 elements per thread).
+template <typename C2, bool INV, int NMAX>
 __device__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw)
 {
     int p = 1;
     for (int ps = 0; ps < sh.npass; ps++) {
         const int R = sh.radix[ps];
         if (R == 4)
-            fft_pass<C2, 4, INV>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 4, INV, NMAX>(buf, sh.nphi, p, tw);
         else if (R == 2)
-            fft_pass<C2, 2, INV>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 2, INV, NMAX>(buf, sh.nphi, p, tw);
         else if (R == 3)
-            fft_pass<C2, 3, INV>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 3, INV, NMAX>(buf, sh.nphi, p, tw);
         else
-            fft_pass<C2, 5, INV>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 5, INV, NMAX>(buf, sh.nphi, p, tw);
         p *= R;
     }
 }
@@ -398,7 +432,7 @@ __device__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw)
 // (W_m - conj W_{n-m})/(2i).  With n = 3L the DFT bin L also holds mode -2L
 // of the square, n conj(G_L)^2, which is subtracted.  Blocks are numbered so
 // that consecutive shells of one pair run on the same XCD (shared L2 lines).
-template <typename T>
+template <typename T, int NMAX>
 __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restrict__ wq,
                                           const typename Mt<T>::c2 *__restrict__ tw,
                                           const T *__restrict__ G, T *__restrict__ F,
@@ -441,7 +475,7 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
         }
     }
     __syncthreads();
-    fft_lds<C2, true>(buf, sh, tw);
+    fft_lds<C2, true, NMAX>(buf, sh, tw);
     if (mode == 1) {
         const long long nr = sh.nring;
         for (int j = tid; j < n; j += 256) {
@@ -457,7 +491,7 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
         buf[j] = z;
     }
     __syncthreads();
-    fft_lds<C2, false>(buf, sh, tw);
+    fft_lds<C2, false, NMAX>(buf, sh, tw);
 
     const T wgt = (T)wq[p];
     const T half = T(0.5);
@@ -490,13 +524,13 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
     }
 }
 
-template <typename T>
+template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict__ wq,
                                               const typename Mt<T>::c2 *__restrict__ tw,
                                               const T *__restrict__ G, T *__restrict__ F,
                                               double *__restrict__ maps, int mode)
 {
-    body_ring<T>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
+    body_ring<T, NMAX>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
 }
 
 // --------------------------------------------------------- Legendre analysis
@@ -516,6 +550,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                                           const double2 *__restrict__ coef,
                                           const double2 *__restrict__ seed,
                                           const int *__restrict__ seedoff,
+                                          const int *__restrict__ cmin,
                                           const double *__restrict__ W,
                                           const double *__restrict__ mu,
                                           const T *__restrict__ F, double2 *__restrict__ part,
@@ -527,6 +562,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     __shared__ T lam[4][32][65];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int4 tl = tiles[bid];
+    if (tl.x < 0) return;  // idle slot of the XCD layout
     const int m = tl.x, lt = tl.y, ct = tl.z;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, k4 = lane >> 4;
@@ -541,41 +577,62 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
         for (int c = 0; c < CF; c++) acc[a][c] = typename M::acc{};
     const int colb = ct * sh.CT + i16;
     const int nchunk = (npair + 63) / 64;
+    const int lblk_end = m + lt * kLTile + kLTile - 1;
     for (int pc = 0; pc < nchunk; pc++) {
+        // polar skip: every pair of the chunk has |lambda| < 1e-30 on these rows
+        const int cm = cmin[(long long)m * nchunk + pc];
+        if (cm > lblk_end) continue;  // block-uniform
+        const bool wrows = wact && cm <= l0w + 31;  // wave-uniform
+        // B operands F_{E/O}[pair][column] of a K-step (4 pairs), loaded one step
+        // ahead; the first step's loads overlap the recurrence below
+        const T *fbase = F + ((long long)m * npair + pc * 64 + k4) * 2 * Cpad + colb;
+        T fE[CF], fO[CF];
+        auto loadF = [&](int kk, T *E, T *O) {
+            const bool ok = pc * 64 + 4 * kk + k4 < npair;
+            const T *f = fbase + (long long)(4 * kk) * 2 * Cpad;
+#pragma unroll
+            for (int cf = 0; cf < CF; cf++) {
+                E[cf] = ok ? f[16 * cf] : T(0);
+                O[cf] = ok ? f[Cpad + 16 * cf] : T(0);
+            }
+        };
+        if (wrows) loadF(0, fE, fO);
         const int p = pc * 64 + lane;
-        const bool pv = wact && p < npair;
-        double a0 = 0.0, a1 = 0.0, xp = 0.0;
+        const bool pv = wrows && p < npair;
+        double a1 = 0.0, a0 = 0.0, xp = 0.0;  // lambda_{l-1}, lambda_{l-2}
         if (pv) {
             const double2 sd = seed[srow * npair + p];
-            a0 = sd.x;
-            a1 = sd.y;
+            a1 = sd.x;
+            a0 = sd.y;
             xp = x[p];
         }
-        lam[wave][0][lane] = (T)a0;
-        lam[wave][1][lane] = (T)a1;
-#pragma unroll 6
-        for (int q = 2; q < 32; q++) {
-            const int l = l0w + q;
-            const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
-            const double v = ab.x * xp * a1 - ab.y * a0;
-            lam[wave][q][lane] = (T)v;
-            a0 = a1;
-            a1 = v;
+        if (wrows) {
+#pragma unroll 4
+            for (int q = 0; q < 32; q++) {
+                const int l = l0w + q;
+                const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
+                const double v = ab.x * xp * a1 - ab.y * a0;
+                lam[wave][q][lane] = (T)v;
+                a0 = a1;
+                a1 = v;
+            }
         }
         __syncthreads();
 #pragma unroll 2
-        for (int kk = 0; kk < 16; kk++) {
+        for (int kk = 0; kk < (wrows ? 16 : 0); kk++) {
+            T gE[CF], gO[CF];
+            if (kk + 1 < 16) loadF(kk + 1, gE, gO);
             const T aE = lam[wave][2 * i16][4 * kk + k4];
             const T aO = lam[wave][2 * i16 + 1][4 * kk + k4];
-            const int pp = pc * 64 + 4 * kk + k4;
-            const T *f = F + ((long long)m * npair + pp) * 2 * Cpad + colb;
-            const bool ok = pp < npair;
 #pragma unroll
             for (int cf = 0; cf < CF; cf++) {
-                const T bE = ok ? f[16 * cf] : T(0);
-                const T bO = ok ? f[Cpad + 16 * cf] : T(0);
-                acc[0][cf] = M::mfma(aE, bE, acc[0][cf]);
-                acc[1][cf] = M::mfma(aO, bO, acc[1][cf]);
+                acc[0][cf] = M::mfma(aE, fE[cf], acc[0][cf]);
+                acc[1][cf] = M::mfma(aO, fO[cf], acc[1][cf]);
+            }
+#pragma unroll
+            for (int cf = 0; cf < CF; cf++) {
+                fE[cf] = gE[cf];
+                fO[cf] = gO[cf];
             }
         }
         __syncthreads();
@@ -646,6 +703,7 @@ __global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__
                                               const double2 *__restrict__ coef,
                                               const double2 *__restrict__ seed,
                                               const int *__restrict__ seedoff,
+                                              const int *__restrict__ cmin,
                                               const double *__restrict__ W,
                                               const double *__restrict__ mu,
                                               const T *__restrict__ F, double2 *__restrict__ part,
@@ -653,8 +711,8 @@ __global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__
                                               const double2 *__restrict__ gT,
                                               const double2 *__restrict__ gE)
 {
-    body_anal<T, CF, MODE>(sh, tiles, x, coef, seed, seedoff, W, mu, F, part, outphi, gT, gE,
-                           blockIdx.x);
+    body_anal<T, CF, MODE>(sh, tiles, x, coef, seed, seedoff, cmin, W, mu, F, part, outphi, gT,
+                           gE, blockIdx.x);
 }
 
 // -------------------------------------------------------------- combine
@@ -755,12 +813,12 @@ __global__ __launch_bounds__(256) void g_synth(const GroupItem *__restrict__ it,
     int lb;
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
-    const int npt = (g.sh.npair + kPairTile - 1) / kPairTile;
-    if (lb >= (g.sh.L + 1) * npt * g.sh.nct) return;
-    body_synth<T, CF>(g.sh, g.b.x, g.b.lmm, g.b.coef, (const T *)g.b.phi, (T *)g.b.G, lb);
+    if (lb >= g.b.nk2) return;
+    body_synth<T, CF>(g.sh, g.b.k2tiles, g.b.x, g.b.seed, g.b.seedoff, g.b.lstart, g.b.coef,
+                      (const T *)g.b.phi, (T *)g.b.G, lb);
 }
 
-template <typename T>
+template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void g_ring(const GroupItem *__restrict__ it,
                                               const int *__restrict__ ord,
                                               const int *__restrict__ off, int n)
@@ -768,7 +826,7 @@ __global__ __launch_bounds__(256) void g_ring(const GroupItem *__restrict__ it,
     int lb;
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
-    body_ring<T>(g.sh, g.b.wq, (const typename Mt<T>::c2 *)g.b.tw, (const T *)g.b.G, (T *)g.b.F,
+    body_ring<T, NMAX>(g.sh, g.b.wq, (const typename Mt<T>::c2 *)g.b.tw, (const T *)g.b.G, (T *)g.b.F,
                  nullptr, 0, lb);
 }
 
@@ -781,8 +839,8 @@ __global__ __launch_bounds__(256) void g_anal(const GroupItem *__restrict__ it,
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
     if (lb >= g.b.nk4) return;
-    body_anal<T, CF, 0>(g.sh, g.b.k4tiles, g.b.x, g.b.coef, g.b.seed, g.b.seedoff, g.b.W, g.b.mu,
-                        (const T *)g.b.F, g.b.part, nullptr, nullptr, nullptr, lb);
+    body_anal<T, CF, 0>(g.sh, g.b.k4tiles, g.b.x, g.b.coef, g.b.seed, g.b.seedoff, g.b.cmin,
+                        g.b.W, g.b.mu, (const T *)g.b.F, g.b.part, nullptr, nullptr, nullptr, lb);
 }
 
 __global__ __launch_bounds__(256) void g_combine(const GroupItem *__restrict__ it,
@@ -798,13 +856,15 @@ __global__ __launch_bounds__(256) void g_combine(const GroupItem *__restrict__ i
 
 // --------------------------------------------------------- recurrence seeds
 
-// One thread per (m, pair): run lambda_lm(x_p) up l and store
-// (lambda_l0, lambda_l0+1) at every l0 = m + 32 u.
+// One thread per (m, pair): run lambda_lm(x_p) up l, store the recurrence
+// state (lambda_{l0-1}, lambda_{l0-2}) entering every l0 = m + 32 u, and the
+// first l where |lambda_lm| exceeds 1e-30.
 __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__restrict__ x,
                                                    const double *__restrict__ lmm,
                                                    const double2 *__restrict__ coef,
                                                    const int *__restrict__ seedoff,
-                                                   double2 *__restrict__ seed)
+                                                   double2 *__restrict__ seed,
+                                                   int *__restrict__ lstart)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int npair = sh.npair, L = sh.L;
@@ -813,20 +873,31 @@ __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__res
     const double xp = x[p];
     double l1 = 0.0, l2 = lmm[(long long)m * npair + p];
     const long long rowm = mrow(L, m, m);
-    double pending = 0.0;
+    int first = L + 1;
     for (int l = m; l <= L; l++) {
-        const double2 ab = coef[rowm + (l - m)];
+        const int d = l - m;
+        if (d % kSeedStride == 0)
+            seed[((long long)seedoff[m] + d / kSeedStride) * npair + p] = make_double2(l1, l2);
+        const double2 ab = coef[rowm + d];
         const double v = ab.x * xp * l1 - ab.y * l2;
+        if (first > L && fabs(v) > kLambdaTiny) first = l;
         l2 = l1;
         l1 = v;
-        const int d = l - m;
-        if (d % kSeedStride == 0) pending = v;
-        if (d % kSeedStride == 1)
-            seed[((long long)seedoff[m] + d / kSeedStride) * npair + p] = make_double2(pending, v);
     }
-    if ((L - m) % kSeedStride == 0)
-        seed[((long long)seedoff[m] + (L - m) / kSeedStride) * npair + p] =
-            make_double2(pending, 0.0);
+    lstart[(long long)m * npair + p] = first;
+}
+
+__global__ __launch_bounds__(256) void k_chunk_min(Shape sh, const int *__restrict__ lstart,
+                                                   int *__restrict__ cmin)
+{
+    const int nchunk = (sh.npair + 63) / 64;
+    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (long long)(sh.L + 1) * nchunk) return;
+    const int c = (int)(t % nchunk), m = (int)(t / nchunk);
+    int v = sh.L + 1;
+    for (int p = c * 64; p < min(sh.npair, c * 64 + 64); p++)
+        v = min(v, lstart[(long long)m * sh.npair + p]);
+    cmin[t] = v;
 }
 
 // ---------------------------------------------------------- layout helpers
@@ -900,7 +971,7 @@ __global__ __launch_bounds__(256) void k_radial_adj(Shape sh, const double *__re
 // transposed synthesis needs c_m sum_pix phibar e^{-i m phi}; with n = 3L the
 // bin L also holds mode -2L of phibar, 2 f_NL w conj(G_L) conj(G2_L) n, which
 // is removed.
-template <typename T>
+template <typename T, int NMAX>
 __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__restrict__ wq,
                                                   const typename Mt<T>::c2 *__restrict__ tw,
                                                   const T *__restrict__ G,
@@ -951,8 +1022,8 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         }
     }
     __syncthreads();
-    fft_lds<C2, true>(b1, sh, tw);
-    fft_lds<C2, true>(b2, sh, tw);
+    fft_lds<C2, true, NMAX>(b1, sh, tw);
+    fft_lds<C2, true, NMAX>(b2, sh, tw);
     const T wpix = (T)wq[p];
     const T two_f = (T)(2.0 * fnl);
     double fb = 0.0;
@@ -968,6 +1039,23 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         ph.y = eq ? T(0) : two_f * f.y * g.y;
         b1[j] = ph;
     }
+    // Phi_L^2 ghat has modes up to 3L along the ring; with n = 3L the pixel sum
+    // also picks up modes +-3L, 2 Re(G_L^2 G2_L) per ring (times n and the
+    // pixel weight), which are removed.
+    if (sh.alias && tid == 0) {
+        const T *g = G + poff + (long long)L * 2 * Cpad;
+        const T *h = G2 + poff + (long long)L * 2 * Cpad;
+        const double Nr = (double)g[0] + (double)g[Cpad], Ni = (double)g[1] + (double)g[Cpad + 1];
+        const double Mr = (double)h[0] + (double)h[Cpad], Mi = (double)h[1] + (double)h[Cpad + 1];
+        // Re(N^2 M) = (Nr^2 - Ni^2) Mr - 2 Nr Ni Mi
+        double a = (Nr * Nr - Ni * Ni) * Mr - 2.0 * Nr * Ni * Mi;
+        if (!eq) {
+            const double Sr = (double)g[0] - (double)g[Cpad], Si = (double)g[1] - (double)g[Cpad + 1];
+            const double Rr = (double)h[0] - (double)h[Cpad], Ri = (double)h[1] - (double)h[Cpad + 1];
+            a += (Sr * Sr - Si * Si) * Rr - 2.0 * Sr * Si * Ri;
+        }
+        fb -= 2.0 * (double)n * (double)wpix * a;
+    }
     red[tid] = fb;
     __syncthreads();
     for (int w = 128; w > 0; w >>= 1) {
@@ -975,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         __syncthreads();
     }
     if (tid == 0) fpart[(long long)p * sh.N + s] = red[0];
-    fft_lds<C2, false>(b1, sh, tw);
+    fft_lds<C2, false, NMAX>(b1, sh, tw);
     const T half = T(0.5);
     for (int m = tid; m <= L; m += 256) {
         const C2 W1 = b1[m];
@@ -1035,7 +1123,9 @@ __global__ __launch_bounds__(256) void k_filter_t(Shape sh, const T *__restrict_
         for (int c = 0; c < 2; c++) acc[a][c] = typename M::acc{};
     const int rowA = row0 + 32 * wr + i16;
     const int colB = ct * 64 + 32 * wc + i16;
-    for (int i0 = 0; i0 < Kpad; i0 += 4) {
+    // lower-triangular F: outputs j >= row0 need rows i >= row0 only
+    const int ibeg = sh.lower ? row0 : 0;
+    for (int i0 = ibeg; i0 < Kpad; i0 += 4) {
         const int i = i0 + k4;
         T av[2], bv[2];
 #pragma unroll
@@ -1108,7 +1198,10 @@ hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s)
 {
     const long long n = (long long)(sh.L + 1) * sh.npair;
     hipLaunchKernelGGL(k_seed_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, sh, b.x, b.lmm,
-                       b.coef, b.seedoff, b.seed);
+                       b.coef, b.seedoff, b.seed, b.lstart);
+    const long long nc = (long long)(sh.L + 1) * ((sh.npair + 63) / 64);
+    hipLaunchKernelGGL(k_chunk_min, dim3(blocks_for(nc, 256)), dim3(256), 0, s, sh, b.lstart,
+                       b.cmin);
     return hipGetLastError();
 }
 
@@ -1140,10 +1233,9 @@ hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, 
 template <typename T, int CF>
 static void synth_t(const Shape &sh, const Bufs &b, const void *phi, void *G, hipStream_t s)
 {
-    const int npt = (sh.npair + kPairTile - 1) / kPairTile;
-    dim3 grid((unsigned)((long long)(sh.L + 1) * npt * sh.nct));
-    hipLaunchKernelGGL((k_synth<T, CF>), grid, dim3(256), 0, s, sh, b.x, b.lmm, b.coef,
-                       (const T *)phi, (T *)G);
+    dim3 grid((unsigned)b.nk2);
+    hipLaunchKernelGGL((k_synth<T, CF>), grid, dim3(256), 0, s, sh, b.k2tiles, b.x, b.seed,
+                       b.seedoff, b.lstart, b.coef, (const T *)phi, (T *)G);
 }
 
 template <typename T>
@@ -1168,28 +1260,42 @@ hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void
     return hipGetLastError();
 }
 
+// Smallest supported maximum ring length covering n.
+static int nmax_for(int n) { return n <= 1024 ? 1024 : n <= 2048 ? 2048 : n <= 4096 ? 4096 : 8192; }
+
+template <typename T, int NMAX>
+static hipError_t ring_t(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                         double *maps, int mode, hipStream_t s)
+{
+    using C2 = typename Mt<T>::c2;
+    const long long nblk = (long long)sh.npair * sh.N;
+    dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
+    const size_t lds = sizeof(C2) * sh.nphi;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_ring<T, NMAX>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_ring<T, NMAX>), grid, dim3(256), lds, s, sh, b.wq, (const C2 *)b.tw,
+                       (const T *)G_in, (T *)F_out, maps, mode);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ring_n(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                         double *maps, int mode, hipStream_t s)
+{
+    switch (nmax_for(sh.nphi)) {
+    case 1024: return ring_t<T, 1024>(sh, b, G_in, F_out, maps, mode, s);
+    case 2048: return ring_t<T, 2048>(sh, b, G_in, F_out, maps, mode, s);
+    case 4096: return ring_t<T, 4096>(sh, b, G_in, F_out, maps, mode, s);
+    default: return ring_t<T, 8192>(sh, b, G_in, F_out, maps, mode, s);
+    }
+}
+
 hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
                        double *maps, int mode, hipStream_t s)
 {
-    const long long nblk = (long long)sh.npair * sh.N;
-    dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
-    if (sh.fp32) {
-        const size_t lds = sizeof(float2) * sh.nphi;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_ring<float>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_ring<float>, grid, dim3(256), lds, s, sh, b.wq,
-                           (const float2 *)b.tw, (const float *)G_in, (float *)F_out, maps, mode);
-    } else {
-        const size_t lds = sizeof(double2) * sh.nphi;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_ring<double>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_ring<double>, grid, dim3(256), lds, s, sh, b.wq,
-                           (const double2 *)b.tw, (const double *)G_in, (double *)F_out, maps,
-                           mode);
-    }
-    return hipGetLastError();
+    return sh.fp32 ? ring_n<float>(sh, b, G_in, F_out, maps, mode, s)
+                   : ring_n<double>(sh, b, G_in, F_out, maps, mode, s);
 }
 
 template <typename T, int CF>
@@ -1199,13 +1305,16 @@ static void anal_t(const Shape &sh, const Bufs &b, const void *F, void *out, int
     dim3 grid(b.nk4);
     if (mode == 0)
         hipLaunchKernelGGL((k_anal<T, CF, 0>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
-                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out, gT, gE);
+                           b.seed, b.seedoff, b.cmin, b.W, b.mu, (const T *)F, b.part,
+                           (T *)out, gT, gE);
     else if (mode == 1)
         hipLaunchKernelGGL((k_anal<T, CF, 1>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
-                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out, gT, gE);
+                           b.seed, b.seedoff, b.cmin, b.W, b.mu, (const T *)F, b.part,
+                           (T *)out, gT, gE);
     else
         hipLaunchKernelGGL((k_anal<T, CF, 2>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
-                           b.seed, b.seedoff, b.W, b.mu, (const T *)F, b.part, (T *)out, gT, gE);
+                           b.seed, b.seedoff, b.cmin, b.W, b.mu, (const T *)F, b.part,
+                           (T *)out, gT, gE);
 }
 
 template <typename T>
@@ -1272,29 +1381,39 @@ hipError_t launch_radial_adj(const Shape &sh, const Bufs &b, const double2 *gT, 
     return hipGetLastError();
 }
 
+template <typename T, int NMAX>
+static hipError_t ring_adj_t(const Shape &sh, const Bufs &b, const void *G, const void *G2,
+                             void *F, double *fpart, double fnl, hipStream_t s)
+{
+    using C2 = typename Mt<T>::c2;
+    const long long nblk = (long long)sh.npair * sh.N;
+    dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
+    const size_t lds = 2 * sizeof(C2) * sh.nphi;
+    if (lds > 65536)
+        (void)hipFuncSetAttribute((const void *)k_ring_adj<T, NMAX>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL((k_ring_adj<T, NMAX>), grid, dim3(256), lds, s, sh, b.wq, (const C2 *)b.tw,
+                       (const T *)G, (const T *)G2, (T *)F, fpart, fnl);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t ring_adj_n(const Shape &sh, const Bufs &b, const void *G, const void *G2,
+                             void *F, double *fpart, double fnl, hipStream_t s)
+{
+    switch (nmax_for(sh.nphi)) {
+    case 1024: return ring_adj_t<T, 1024>(sh, b, G, G2, F, fpart, fnl, s);
+    case 2048: return ring_adj_t<T, 2048>(sh, b, G, G2, F, fpart, fnl, s);
+    case 4096: return ring_adj_t<T, 4096>(sh, b, G, G2, F, fpart, fnl, s);
+    default: return ring_adj_t<T, 8192>(sh, b, G, G2, F, fpart, fnl, s);
+    }
+}
+
 hipError_t launch_ring_adj(const Shape &sh, const Bufs &b, const void *G, const void *G2, void *F,
                            double *fpart, double fnl, hipStream_t s)
 {
-    const long long nblk = (long long)sh.npair * sh.N;
-    dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
-    if (sh.fp32) {
-        const size_t lds = 2 * sizeof(float2) * sh.nphi;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_ring_adj<float>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_ring_adj<float>, grid, dim3(256), lds, s, sh, b.wq,
-                           (const float2 *)b.tw, (const float *)G, (const float *)G2, (float *)F,
-                           fpart, fnl);
-    } else {
-        const size_t lds = 2 * sizeof(double2) * sh.nphi;
-        if (lds > 65536)
-            (void)hipFuncSetAttribute((const void *)k_ring_adj<double>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_ring_adj<double>, grid, dim3(256), lds, s, sh, b.wq,
-                           (const double2 *)b.tw, (const double *)G, (const double *)G2,
-                           (double *)F, fpart, fnl);
-    }
-    return hipGetLastError();
+    return sh.fp32 ? ring_adj_n<float>(sh, b, G, G2, F, fpart, fnl, s)
+                   : ring_adj_n<double>(sh, b, G, G2, F, fpart, fnl, s);
 }
 
 hipError_t launch_filter_t(const Shape &sh, const Bufs &b, const void *phibar, void *gout,
@@ -1325,7 +1444,7 @@ long long group_blocks(int stage, const Shape &sh, const Bufs &b)
     case GS_RADIAL_LIN:
     case GS_COMBINE: return (sh.nlm + 255) / 256;
     case GS_FILTER: return (long long)b.nk1 * (b.Mpad / 64);
-    case GS_SYNTH: return (long long)(sh.L + 1) * ((sh.npair + kPairTile - 1) / kPairTile) * sh.nct;
+    case GS_SYNTH: return b.nk2;
     case GS_RING: return ((long long)sh.npair * sh.N + 7) / 8 * 8;
     case GS_ANAL: return b.nk4;
     default: return 0;
@@ -1351,7 +1470,18 @@ static void group_t(int stage, int CF, const GroupItem *it, const int *ord, cons
         hipLaunchKernelGGL(g_radial_lin<T>, grid, dim3(256), 0, s, it, ord, off, n);
         break;
     case GS_FILTER: hipLaunchKernelGGL(g_filter<T>, grid, dim3(256), 0, s, it, ord, off, n); break;
-    case GS_RING: hipLaunchKernelGGL(g_ring<T>, grid, dim3(256), lds, s, it, ord, off, n); break;
+    case GS_RING: {
+        const int nmax = nmax_for((int)(lds / sizeof(typename Mt<T>::c2)));
+        if (nmax == 1024)
+            hipLaunchKernelGGL((g_ring<T, 1024>), grid, dim3(256), lds, s, it, ord, off, n);
+        else if (nmax == 2048)
+            hipLaunchKernelGGL((g_ring<T, 2048>), grid, dim3(256), lds, s, it, ord, off, n);
+        else if (nmax == 4096)
+            hipLaunchKernelGGL((g_ring<T, 4096>), grid, dim3(256), lds, s, it, ord, off, n);
+        else
+            hipLaunchKernelGGL((g_ring<T, 8192>), grid, dim3(256), lds, s, it, ord, off, n);
+        break;
+    }
     case GS_COMBINE: hipLaunchKernelGGL(g_combine, grid, dim3(256), 0, s, it, ord, off, n); break;
     default:
         switch (CF) {
@@ -1376,14 +1506,21 @@ hipError_t launch_group(int stage, int fp32, int CF, const GroupItem *items, con
     return hipGetLastError();
 }
 
+template <typename T>
+static hipError_t prep_ring_t(size_t lds)
+{
+    const int nmax = nmax_for((int)(lds / sizeof(typename Mt<T>::c2)));
+    const void *f = nmax == 1024   ? (const void *)g_ring<T, 1024>
+                    : nmax == 2048 ? (const void *)g_ring<T, 2048>
+                    : nmax == 4096 ? (const void *)g_ring<T, 4096>
+                                   : (const void *)g_ring<T, 8192>;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
 hipError_t prepare_group_ring(int fp32, size_t lds)
 {
     if (lds <= 65536) return hipSuccess;
-    if (fp32)
-        return hipFuncSetAttribute((const void *)g_ring<float>,
-                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    return hipFuncSetAttribute((const void *)g_ring<double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return fp32 ? prep_ring_t<float>(lds) : prep_ring_t<double>(lds);
 }
 
 }  // namespace fnl

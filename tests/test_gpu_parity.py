@@ -160,3 +160,20 @@ def test_paper_scale_sampled_shells(fs, orc, precision):
     got = sim.forward(_dev(noise, precision), cfg["fnl"], want_nl=True)
     ref = _oracle(orc, p, L, alpha=al, beta=be).forward(noise, cfg["fnl"])
     _check_all(got, ref, L, TOL[precision], f"paper {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_dense_filter(fs, orc, precision):
+    """The ABI takes any real filter, not only a Cholesky factor: a dense F
+    (upper triangle non-zero) takes the full contraction."""
+    L, N = 20, 70
+    p = _problem(L, N)
+    rng = np.random.default_rng(5)
+    F = p["filter"] + np.triu(rng.standard_normal((L + 1, N, N)), 1) * 1e-6
+    sim = fs.Simulator(L, p["r"], p["w"], F, p["alpha"], p["beta"], precision=precision)
+    noise = inputs.noise(L, N, 31)
+    if precision == "fp32":
+        noise = noise.astype(np.complex64).astype(np.complex128)
+    got = sim.forward(_dev(noise, precision), 60.0, want_nl=True)
+    ref = orc.Problem(L, p["r"], p["w"], F, p["alpha"], p["beta"]).forward(noise, 60.0)
+    _check_all(got, ref, L, TOL[precision], f"dense filter {precision}")
