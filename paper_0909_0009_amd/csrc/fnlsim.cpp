@@ -276,12 +276,14 @@ int build_precision_tables(sim_ctx *c, const double *filter)
     rc = upload(c, &b.tw, tw.data(), tw.size());
     if (rc) return rc;
     const size_t elem = sizeof(T);
-    const size_t phib = elem * (size_t)sh.nlm * sh.Cpad;
+    // 8 zero rows past the last m block: the synthesis reads whole K-steps
+    const size_t phib = elem * ((size_t)sh.nlm + 8) * sh.Cpad;
     if ((rc = alloc_zero(c, &b.phi, phib))) return rc;
     if ((rc = alloc_zero(c, &b.scratch, phib))) return rc;
     const size_t gb = elem * (size_t)sh.npair * (L + 1) * 2 * sh.Cpad;
     if ((rc = alloc_zero(c, &b.G, gb))) return rc;
-    if ((rc = alloc_zero(c, &b.F, gb))) return rc;
+    // 64 zero pairs past the last m: the analysis reads whole 64-pair chunks
+    if ((rc = alloc_zero(c, &b.F, gb + elem * (size_t)64 * 2 * sh.Cpad))) return rc;
     return SIM_OK;
 }
 
@@ -445,7 +447,9 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     // which read the same F_m columns
     std::vector<int4> k2, k4;
     {
-        const int npt = (np + fnl::kPairTile - 1) / fnl::kPairTile;
+        // pairs per synthesis wave: 64 (FP32) or 32 (FP64)
+        const int pw = sh.fp32 ? 64 : 32;
+        const int npt = (np + pw - 1) / pw;
         std::vector<std::vector<int4>> g2, g4;
         std::vector<double> w2, w4;
         for (int m = 0; m <= L; m++)

@@ -10,7 +10,6 @@ namespace fnl {
 
 constexpr int kMaxPhi = 8192;   // longest ring the in-LDS FFT handles
 constexpr int kMaxPasses = 16;
-constexpr int kPairTile = 64;   // ring pairs per synthesis workgroup
 constexpr int kLTile = 128;     // l rows per analysis workgroup (4 waves x 32)
 constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
 constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)

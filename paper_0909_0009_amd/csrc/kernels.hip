@@ -166,11 +166,21 @@ __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__re
 
 // -------------------------------------------------------- Legendre synthesis
 
-// Block = (m, 64 ring pairs, column tile of 16 CF columns); wave w owns 16
-// pairs.  The contraction index is l in steps of 8: four even and four odd
-// l - m per step.  Every lane runs the FP64 recurrence for its pair (lane
-// mod 16) and keeps the value its MFMA k-slot (lane / 16) needs; the
-// coefficient loads are wave-uniform.
+// Pairs per synthesis wave: 64 in FP32, 32 in FP64 (register budget of the
+// accumulators).  A synthesis workgroup is one wave.
+template <typename T> constexpr int synth_pw() { return sizeof(T) == 8 ? 32 : 64; }
+// LDS row stride of the transposed lambda tile (FP32: rows 2k apart land in
+// disjoint bank quarters, so the A-fragment reads are conflict-free)
+template <typename T> constexpr int synth_ld() { return sizeof(T) == 8 ? 36 : 72; }
+
+// Block = (m, PW ring pairs, column tile of 16 CF columns), one wave.  The
+// contraction index is l in K-steps of 8 (four even and four odd l - m).
+// Lane q runs the FP64 three-term recurrence for pair q (mod PW) from the
+// stored state; its 8 values per K-step go through a double-buffered LDS tile
+// into the MFMA A layout (lane = (pair, k-slot)), so every recurrence step
+// feeds NF = PW/16 pair fragments x 2 parities x CF column fragments of
+// MFMAs.  The wave starts at the first stored state below the first l where
+// any of its pairs has |lambda_lm| > 1e-30 (polar skip).
 template <typename T, int CF>
 __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restrict__ tiles,
                                            const double *__restrict__ x,
@@ -181,20 +191,24 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
                                            const T *__restrict__ phi, T *__restrict__ G, int bid)
 {
     using M = Mt<T>;
+    constexpr int PW = synth_pw<T>();
+    constexpr int NF = PW / 16;
+    constexpr int LD = synth_ld<T>();
+    __shared__ T lamT[2][8][LD];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int4 tl = tiles[bid];
     if (tl.x < 0) return;  // idle slot of the XCD layout
     const int m = tl.x, pt = tl.y, ct = tl.z;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     const int i16 = lane & 15, k4 = lane >> 4;
-    const int p = pt * kPairTile + wave * 16 + i16;
+    const int p0 = pt * PW;
+    const int p = p0 + (lane % PW);
     const bool pv = p < npair;
+    const int nfa = min(NF, (npair - p0 + 15) / 16);  // fragments holding a pair
     const double xp = pv ? x[p] : 0.0;
-    // polar skip: start at the seed row below the first l where any of the
-    // wave's 16 pairs has |lambda_lm| > 1e-30 (wave-uniform)
     int ls = pv ? lstart[(long long)m * npair + p] : L + 1;
 #pragma unroll
-    for (int o = 1; o < 16; o <<= 1) ls = min(ls, __shfl_xor(ls, o));
+    for (int o = 1; o < 64; o <<= 1) ls = min(ls, __shfl_xor(ls, o));
     const int u0 = ls <= L ? (ls - m) / kSeedStride : 0;
     double l1 = 0.0, l2 = 0.0;
     if (pv && ls <= L) {
@@ -202,31 +216,30 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
         l1 = st.x;
         l2 = st.y;
     }
-    typename M::acc acc[2][CF];
+    typename M::acc acc[NF][2][CF];
 #pragma unroll
-    for (int a = 0; a < 2; a++)
+    for (int f = 0; f < NF; f++)
 #pragma unroll
-        for (int c = 0; c < CF; c++) acc[a][c] = typename M::acc{};
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int c = 0; c < CF; c++) acc[f][a][c] = typename M::acc{};
     const long long rowm = mrow(L, m, m);
     const int colb = ct * sh.CT + i16;
     const int lbeg = ls <= L ? m + u0 * kSeedStride : L + 1;
-    // B operands of a K-step: rows l0 + 2 k4 (even l - m) and l0 + 2 k4 + 1 (odd),
-    // loaded one step ahead so the loads overlap the recurrence and the MFMAs
+    // B operands of a K-step: rows l0 + 2 k4 (even l - m) and l0 + 2 k4 + 1 (odd).
+    // Rows past l = L belong to the next m (or to the zero padding after the
+    // last one) and meet lambda = 0 exactly, so no per-lane bounds are needed.
     const T *colbase = phi + rowm * Cpad + colb;
-    T bE[CF], bO[CF];
     auto loadB = [&](int l0, T *E, T *O) {
-        const int lE = l0 + 2 * k4;
-        const T *rE = colbase + (long long)(lE - m) * Cpad;
+        const T *rE = colbase + (long long)(l0 + 2 * k4 - m) * Cpad;
 #pragma unroll
         for (int cf = 0; cf < CF; cf++) {
-            E[cf] = lE <= L ? rE[16 * cf] : T(0);
-            O[cf] = lE + 1 <= L ? rE[Cpad + 16 * cf] : T(0);
+            E[cf] = rE[16 * cf];
+            O[cf] = rE[Cpad + 16 * cf];
         }
     };
-    if (lbeg <= L) loadB(lbeg, bE, bO);
-    for (int l0 = lbeg; l0 <= L; l0 += 8) {
-        T nE[CF], nO[CF];
-        if (l0 + 8 <= L) loadB(l0 + 8, nE, nO);
+    int buf = 0;
+    auto kstep = [&](int l0, const T *E, const T *O) {
         double v[8];
 #pragma unroll
         for (int q = 0; q < 8; q++) {
@@ -237,41 +250,66 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
             l2 = l1;
             l1 = nv;
         }
-        const double e = k4 == 0 ? v[0] : k4 == 1 ? v[2] : k4 == 2 ? v[4] : v[6];
-        const double o = k4 == 0 ? v[1] : k4 == 1 ? v[3] : k4 == 2 ? v[5] : v[7];
-        const T ae = (T)e, ao = (T)o;
+        if (lane < PW) {
 #pragma unroll
-        for (int cf = 0; cf < CF; cf++) {
-            acc[0][cf] = M::mfma(ae, bE[cf], acc[0][cf]);
-            acc[1][cf] = M::mfma(ao, bO[cf], acc[1][cf]);
+            for (int q = 0; q < 8; q++) lamT[buf][q][lane] = (T)v[q];
         }
+        __syncthreads();  // one wave: orders the tile writes before the reads
 #pragma unroll
-        for (int cf = 0; cf < CF; cf++) {
-            bE[cf] = nE[cf];
-            bO[cf] = nO[cf];
-        }
-    }
+        for (int f = 0; f < NF; f++) {
+            if (f < nfa) {
+                const T aE = lamT[buf][2 * k4][16 * f + i16];
+                const T aO = lamT[buf][2 * k4 + 1][16 * f + i16];
 #pragma unroll
-    for (int par = 0; par < 2; par++)
-#pragma unroll
-        for (int cf = 0; cf < CF; cf++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int pair = pt * kPairTile + wave * 16 + M::row(k4, r);
-                if (pair < npair)
-                    G[(((long long)pair * (L + 1) + m) * 2 + par) * Cpad + colb + 16 * cf] =
-                        acc[par][cf][r];
+                for (int cf = 0; cf < CF; cf++) {
+                    acc[f][0][cf] = M::mfma(aE, E[cf], acc[f][0][cf]);
+                    acc[f][1][cf] = M::mfma(aO, O[cf], acc[f][1][cf]);
+                }
             }
+        }
+        buf ^= 1;
+    };
+    // two K-steps per trip with the operand buffers swapping roles
+    T bE[CF], bO[CF], nE[CF], nO[CF];
+    const int nks = lbeg <= L ? (L - lbeg) / 8 + 1 : 0;
+    int l0 = lbeg;
+    if (nks > 0) loadB(l0, bE, bO);
+    for (int it = 0; it < nks / 2; it++) {
+        loadB(l0 + 8, nE, nO);
+        kstep(l0, bE, bO);
+        if (2 * it + 2 < nks) loadB(l0 + 16, bE, bO);
+        kstep(l0 + 8, nE, nO);
+        l0 += 16;
+    }
+    if (nks & 1) kstep(l0, bE, bO);
+#pragma unroll
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+        for (int par = 0; par < 2; par++)
+#pragma unroll
+            for (int cf = 0; cf < CF; cf++)
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const int pair = p0 + 16 * f + M::row(k4, r);
+                    if (pair < npair)
+                        G[(((long long)pair * (L + 1) + m) * 2 + par) * Cpad + colb + 16 * cf] =
+                            acc[f][par][cf][r];
+                }
 }
 
+// waves per SIMD the synthesis register budget is held to
+template <typename T> constexpr int synth_waves() { return 2; }
+
 template <typename T, int CF>
-__global__ __launch_bounds__(256) void k_synth(Shape sh, const int4 *__restrict__ tiles,
-                                               const double *__restrict__ x,
-                                               const double2 *__restrict__ seed,
-                                               const int *__restrict__ seedoff,
-                                               const int *__restrict__ lstart,
-                                               const double2 *__restrict__ coef,
-                                               const T *__restrict__ phi, T *__restrict__ G)
+__global__ __launch_bounds__(64, synth_waves<T>()) void k_synth(Shape sh,
+                                                               const int4 *__restrict__ tiles,
+                                                               const double *__restrict__ x,
+                                                               const double2 *__restrict__ seed,
+                                                               const int *__restrict__ seedoff,
+                                                               const int *__restrict__ lstart,
+                                                               const double2 *__restrict__ coef,
+                                                               const T *__restrict__ phi,
+                                                               T *__restrict__ G)
 {
     body_synth<T, CF>(sh, tiles, x, seed, seedoff, lstart, coef, phi, G, blockIdx.x);
 }
@@ -364,26 +402,47 @@ template <typename C2, int R, bool INV> __device__ inline void dft_small(C2 *a)
 // Butterfly i (k = i mod p) reads x_t = buf[i + t n/R], twists it by
 // w^{t k n/(p R)} and writes DFT_R(x)_t to buf[(i - k) R + k + t p].  All reads
 // finish before any write, so the pass works in place.
+// k = i mod p; p is a power of two in every pass but a trailing radix-3/5
+// one, so the mask path is the common one (p is block-uniform).
+__device__ inline int mod_p(int i, int p) { return (p & (p - 1)) == 0 ? (i & (p - 1)) : i % p; }
+
 template <typename C2, int R, bool INV, int NMAX>
 __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
 {
     constexpr int MAXB = (NMAX / R + 255) / 256;
     const int nb = n / R;
     const int tstep = n / (p * R);
+    // when p divides 256, k = i mod p is the same for every round c of this
+    // thread, so its twiddles are loaded once
+    const bool shared_k = (256 % p) == 0;
+    C2 w0[R];
+    if (shared_k) {
+        const int k = mod_p(threadIdx.x, p);
+#pragma unroll
+        for (int t = 1; t < R; t++) {
+            w0[t] = tw[t * k * tstep];
+            if (INV) w0[t].y = -w0[t].y;
+        }
+    }
     C2 y[MAXB][R];
 #pragma unroll
     for (int c = 0; c < MAXB; c++) {
         const int i = threadIdx.x + c * 256;
         if (i < nb) {
-            const int k = i % p;
             C2 xv[R];
 #pragma unroll
             for (int t = 0; t < R; t++) xv[t] = buf[i + t * nb];
+            if (shared_k) {
 #pragma unroll
-            for (int t = 1; t < R; t++) {
-                C2 w = tw[t * k * tstep];
-                if (INV) w.y = -w.y;
-                xv[t] = cmul(xv[t], w);
+                for (int t = 1; t < R; t++) xv[t] = cmul(xv[t], w0[t]);
+            } else {
+                const int k = mod_p(i, p);
+#pragma unroll
+                for (int t = 1; t < R; t++) {
+                    C2 w = tw[t * k * tstep];
+                    if (INV) w.y = -w.y;
+                    xv[t] = cmul(xv[t], w);
+                }
             }
             dft_small<C2, R, INV>(xv);
 #pragma unroll
@@ -395,7 +454,7 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
     for (int c = 0; c < MAXB; c++) {
         const int i = threadIdx.x + c * 256;
         if (i < nb) {
-            const int k = i % p;
+            const int k = mod_p(i, p);
             const int j = (i - k) * R + k;
 #pragma unroll
             for (int t = 0; t < R; t++) buf[j + t * p] = y[c][t];
@@ -450,13 +509,13 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
     const int tid = threadIdx.x;
     const bool eq = sh.equator && p == sh.npair - 1;
 
-    for (int q = tid; q < n; q += 256) {
+    // bins (L, n - L) are empty; the loop below writes every other bin
+    for (int q = L + 1 + tid; q < n - L; q += 256) {
         C2 z;
         z.x = T(0);
         z.y = T(0);
         buf[q] = z;
     }
-    __syncthreads();
     const T *Gp = G + (long long)p * (L + 1) * 2 * Cpad + 2 * s;
     for (int m = tid; m <= L; m += 256) {
         const T *g = Gp + (long long)m * 2 * Cpad;
@@ -584,16 +643,17 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
         if (cm > lblk_end) continue;  // block-uniform
         const bool wrows = wact && cm <= l0w + 31;  // wave-uniform
         // B operands F_{E/O}[pair][column] of a K-step (4 pairs), loaded one step
-        // ahead; the first step's loads overlap the recurrence below
+        // ahead; the first step's loads overlap the recurrence below.  Pairs
+        // past the last one read the next m (or the zero padding after the
+        // last m) and meet lambda = 0 exactly.
         const T *fbase = F + ((long long)m * npair + pc * 64 + k4) * 2 * Cpad + colb;
-        T fE[CF], fO[CF];
+        T fE[CF], fO[CF], gE[CF], gO[CF];
         auto loadF = [&](int kk, T *E, T *O) {
-            const bool ok = pc * 64 + 4 * kk + k4 < npair;
             const T *f = fbase + (long long)(4 * kk) * 2 * Cpad;
 #pragma unroll
             for (int cf = 0; cf < CF; cf++) {
-                E[cf] = ok ? f[16 * cf] : T(0);
-                O[cf] = ok ? f[Cpad + 16 * cf] : T(0);
+                E[cf] = f[16 * cf];
+                O[cf] = f[Cpad + 16 * cf];
             }
         };
         if (wrows) loadF(0, fE, fO);
@@ -618,22 +678,21 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
             }
         }
         __syncthreads();
-#pragma unroll 2
-        for (int kk = 0; kk < (wrows ? 16 : 0); kk++) {
-            T gE[CF], gO[CF];
-            if (kk + 1 < 16) loadF(kk + 1, gE, gO);
+        // 16 K-steps in pairs, the operand buffers swapping roles
+        auto kstep = [&](int kk, const T *E, const T *O) {
             const T aE = lam[wave][2 * i16][4 * kk + k4];
             const T aO = lam[wave][2 * i16 + 1][4 * kk + k4];
 #pragma unroll
             for (int cf = 0; cf < CF; cf++) {
-                acc[0][cf] = M::mfma(aE, fE[cf], acc[0][cf]);
-                acc[1][cf] = M::mfma(aO, fO[cf], acc[1][cf]);
+                acc[0][cf] = M::mfma(aE, E[cf], acc[0][cf]);
+                acc[1][cf] = M::mfma(aO, O[cf], acc[1][cf]);
             }
-#pragma unroll
-            for (int cf = 0; cf < CF; cf++) {
-                fE[cf] = gE[cf];
-                fO[cf] = gO[cf];
-            }
+        };
+        for (int kk = 0; kk < (wrows ? 16 : 0); kk += 2) {
+            loadF(kk + 1, gE, gO);
+            kstep(kk, fE, fO);
+            if (kk + 2 < 16) loadF(kk + 2, fE, fO);
+            kstep(kk + 1, gE, gO);
         }
         __syncthreads();
     }
@@ -806,7 +865,7 @@ __global__ __launch_bounds__(256) void g_filter(const GroupItem *__restrict__ it
 }
 
 template <typename T, int CF>
-__global__ __launch_bounds__(256) void g_synth(const GroupItem *__restrict__ it,
+__global__ __launch_bounds__(64, synth_waves<T>()) void g_synth(const GroupItem *__restrict__ it,
                                                const int *__restrict__ ord,
                                                const int *__restrict__ off, int n)
 {
@@ -1234,7 +1293,7 @@ template <typename T, int CF>
 static void synth_t(const Shape &sh, const Bufs &b, const void *phi, void *G, hipStream_t s)
 {
     dim3 grid((unsigned)b.nk2);
-    hipLaunchKernelGGL((k_synth<T, CF>), grid, dim3(256), 0, s, sh, b.k2tiles, b.x, b.seed,
+    hipLaunchKernelGGL((k_synth<T, CF>), grid, dim3(64), 0, s, sh, b.k2tiles, b.x, b.seed,
                        b.seedoff, b.lstart, b.coef, (const T *)phi, (T *)G);
 }
 
@@ -1456,7 +1515,7 @@ static void group_cf(int stage, const GroupItem *it, const int *ord, const int *
                      dim3 grid, hipStream_t s)
 {
     if (stage == GS_SYNTH)
-        hipLaunchKernelGGL((g_synth<T, CF>), grid, dim3(256), 0, s, it, ord, off, n);
+        hipLaunchKernelGGL((g_synth<T, CF>), grid, dim3(64), 0, s, it, ord, off, n);
     else
         hipLaunchKernelGGL((g_anal<T, CF>), grid, dim3(256), 0, s, it, ord, off, n);
 }
