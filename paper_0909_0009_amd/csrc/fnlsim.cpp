@@ -449,6 +449,8 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     {
         // pairs per synthesis wave: 64 (FP32) or 32 (FP64)
         const int pw = sh.fp32 ? 64 : 32;
+        // l rows per analysis wave: 128 (FP32) or 64 (FP64)
+        const int rw = sh.fp32 ? 128 : 64;
         const int npt = (np + pw - 1) / pw;
         std::vector<std::vector<int4>> g2, g4;
         std::vector<double> w2, w4;
@@ -456,7 +458,7 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             for (int ct = 0; ct < sh.nct; ct++) {
                 std::vector<int4> a, c4;
                 for (int pt = 0; pt < npt; pt++) a.push_back(make_int4(m, pt, ct, 0));
-                for (int lt = 0; lt < (L - m + 1 + fnl::kLTile - 1) / fnl::kLTile; lt++)
+                for (int lt = 0; lt < (L - m + 1 + rw - 1) / rw; lt++)
                     c4.push_back(make_int4(m, lt, ct, 0));
                 g2.push_back(a);
                 w2.push_back((double)(L - m + 1));
@@ -506,7 +508,7 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
         b.seed = (double2 *)p;
         if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * np))) goto bad;
         b.lstart = (int *)p;
-        if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 63) / 64)))) goto bad;
+        if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 31) / 32)))) goto bad;
         b.cmin = (int *)p;
         if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)sh.nct * 2 * sh.nlm))) goto bad;
         b.part = (double2 *)p;

@@ -10,7 +10,6 @@ namespace fnl {
 
 constexpr int kMaxPhi = 8192;   // longest ring the in-LDS FFT handles
 constexpr int kMaxPasses = 16;
-constexpr int kLTile = 128;     // l rows per analysis workgroup (4 waves x 32)
 constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
 constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)
 
@@ -59,7 +58,7 @@ struct Bufs {
                        // entering l0 = m + 32u ((0, lambda_mm) for u = 0)
     int *seedoff;      // [L+2] first seed row of each m
     int *lstart;       // [L+1][npair] first l with |lambda_lm(x_p)| > 1e-30 (L+1 if none)
-    int *cmin;         // [L+1][ceil(npair/64)] min of lstart over each 64-pair chunk
+    int *cmin;         // [L+1][ceil(npair/32)] min of lstart over each 32-pair chunk
     int2 *k1tiles;     // [nk1] (l, column tile) of each filter workgroup
     int4 *k2tiles;     // [nk2] synthesis blocks (m, pair tile, column tile, 0)
     int4 *k4tiles;     // [nk4] analysis blocks (m, l tile, column tile, 0)

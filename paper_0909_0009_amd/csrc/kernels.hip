@@ -463,11 +463,99 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
     __syncthreads();
 }
 
+// Compile-time pass of radix R with stride P over an N-point ring: the same
+// Stockham step as fft_pass with every index folded to constants.
+template <typename C2, int R, bool INV, int N, int P>
+__device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw)
+{
+    constexpr int NB = N / R;
+    constexpr int TSTEP = N / (P * R);
+    constexpr int MAXB = (NB + 255) / 256;
+    constexpr bool SHARED_K = (256 % P) == 0;
+    C2 w0[R];
+    if constexpr (SHARED_K && P > 1) {
+        const int k = threadIdx.x % P;
+#pragma unroll
+        for (int t = 1; t < R; t++) {
+            w0[t] = tw[t * k * TSTEP];
+            if (INV) w0[t].y = -w0[t].y;
+        }
+    }
+    C2 y[MAXB][R];
+#pragma unroll
+    for (int c = 0; c < MAXB; c++) {
+        const int i = threadIdx.x + c * 256;
+        if (NB % 256 == 0 || i < NB) {
+            C2 xv[R];
+#pragma unroll
+            for (int t = 0; t < R; t++) xv[t] = buf[i + t * NB];
+            if constexpr (P > 1) {
+                if constexpr (SHARED_K) {
+#pragma unroll
+                    for (int t = 1; t < R; t++) xv[t] = cmul(xv[t], w0[t]);
+                } else {
+                    const int k = i % P;
+#pragma unroll
+                    for (int t = 1; t < R; t++) {
+                        C2 w = tw[t * k * TSTEP];
+                        if (INV) w.y = -w.y;
+                        xv[t] = cmul(xv[t], w);
+                    }
+                }
+            }
+            dft_small<C2, R, INV>(xv);
+#pragma unroll
+            for (int t = 0; t < R; t++) y[c][t] = xv[t];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < MAXB; c++) {
+        const int i = threadIdx.x + c * 256;
+        if (NB % 256 == 0 || i < NB) {
+            const int k = i % P;
+            const int j = (i - k) * R + k;
+#pragma unroll
+            for (int t = 0; t < R; t++) buf[j + t * P] = y[c][t];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename C2, bool INV, int N, int P, int R, int... Rest>
+__device__ __forceinline__ void fft_static(C2 *buf, const C2 *__restrict__ tw)
+{
+    fft_pass_c<C2, R, INV, N, P>(buf, tw);
+    if constexpr (sizeof...(Rest) > 0) fft_static<C2, INV, N, P * R, Rest...>(buf, tw);
+}
+
+// Ring lengths with a compile-time plan (the 3L grids of lmax 256..2048);
+// returns false for other lengths, which take the run-time plan.
+// Only lengths in (NMAX/2, NMAX] are planned in an instantiation: shorter
+// rings run in the instantiation below it, and a plan longer than NMAX would
+// need more registers than the kernel reserves.
+template <typename C2, bool INV, int NMAX>
+__device__ __forceinline__ bool fft_planned(C2 *buf, int n, const C2 *__restrict__ tw)
+{
+    if constexpr (NMAX == 1024) {
+        if (n == 768) { fft_static<C2, INV, 768, 1, 4, 4, 4, 4, 3>(buf, tw); return true; }
+        if (n == 1024) { fft_static<C2, INV, 1024, 1, 4, 4, 4, 4, 4>(buf, tw); return true; }
+    } else if constexpr (NMAX == 2048) {
+        if (n == 1536) { fft_static<C2, INV, 1536, 1, 4, 4, 4, 4, 2, 3>(buf, tw); return true; }
+    } else if constexpr (NMAX == 4096) {
+        if (n == 3072) { fft_static<C2, INV, 3072, 1, 4, 4, 4, 4, 4, 3>(buf, tw); return true; }
+    } else if constexpr (NMAX == 8192) {
+        if (n == 6144) { fft_static<C2, INV, 6144, 1, 4, 4, 4, 4, 4, 2, 3>(buf, tw); return true; }
+    }
+    return false;
+}
+
 // NMAX: longest ring this instantiation handles (registers are reserved for
 // NMAX / 256 elements per thread).
 template <typename C2, bool INV, int NMAX>
 __device__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw)
 {
+    if (fft_planned<C2, INV, NMAX>(buf, sh.nphi, tw)) return;
     int p = 1;
     for (int ps = 0; ps < sh.npass; ps++) {
         const int R = sh.radix[ps];
@@ -594,15 +682,24 @@ __global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict
 
 // --------------------------------------------------------- Legendre analysis
 
-// Block = (m, 128 l rows, column tile).  Wave w owns rows l0w .. l0w+31,
-// l0w = m + 128 t + 32 w: 16 rows with l - m even (against F_E) and 16 odd
-// (against F_O).  For each chunk of 64 ring pairs the wave runs the FP64
-// recurrence with one lane per pair, starting from the stored seeds at l0w,
-// stages the 32 x 64 values in LDS and reads them back in the MFMA A layout
-// (lane = (row, pair)).  mode 0 folds the radial sum into the epilogue:
-// part[ct][X][idx(l, m)] = sum_s W^X_ls Phi_NL,lm(s) over the tile's shells.
-// mode 2 (reverse pass): per-shell output plus the direct cotangent
-// sum_X W^X_ls abar^X_lm, no mean handling.
+// Rows per analysis wave: 128 in FP32, 64 in FP64 (register budget of the
+// accumulators); pairs per chunk; LDS row strides that keep the A-fragment
+// reads free of bank conflicts.
+template <typename T> constexpr int anal_rw() { return sizeof(T) == 8 ? 64 : 128; }
+template <typename T> constexpr int anal_ld() { return sizeof(T) == 8 ? 33 : 34; }
+constexpr int kAnalPC = 32;
+
+// Block = (m, RW l rows from l0 = m + RW t, column tile), one wave.  Rows with
+// l - m even meet F_E, odd ones F_O: NF = RW/32 fragments of 16 rows per
+// parity.  For each chunk of 32 ring pairs, lane (half h, pair q) runs the
+// FP64 recurrence over rows [h RW/2, (h+1) RW/2) of pair q from the stored
+// state, writes the values to an LDS tile, and the wave reads them back in the
+// MFMA A layout (lane = (row, pair)).  Chunks and fragments whose rows all lie
+// below the first l where any pair of the chunk has |lambda| > 1e-30 are
+// skipped (polar skip).  mode 0 folds the radial sum into the epilogue:
+// part[ct][X][idx(l, m)] = sum_s W^X_ls Phi_NL,lm(s) over the tile's shells;
+// mode 1 writes Phi_NL per shell; mode 2 (reverse pass) writes the per-shell
+// output plus the direct cotangent sum_X W^X_ls abar^X_lm, no mean handling.
 template <typename T, int CF, int MODE>
 __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restrict__ tiles,
                                           const double *__restrict__ x,
@@ -618,36 +715,42 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                                           const double2 *__restrict__ gE, int bid)
 {
     using M = Mt<T>;
-    __shared__ T lam[4][32][65];
+    constexpr int RW = anal_rw<T>();
+    constexpr int NF = RW / 32;
+    constexpr int LD = anal_ld<T>();
+    __shared__ T lam[RW][LD];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int4 tl = tiles[bid];
     if (tl.x < 0) return;  // idle slot of the XCD layout
     const int m = tl.x, lt = tl.y, ct = tl.z;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x;
     const int i16 = lane & 15, k4 = lane >> 4;
-    const int l0w = m + lt * kLTile + wave * 32;
-    const bool wact = l0w <= L;
+    const int half = lane >> 5, pl = lane & 31;
+    const int l0w = m + lt * RW;
+    const int lh = l0w + half * (RW / 2);  // first recurrence row of this lane
+    const bool hact = lh <= L;
     const long long rowm = mrow(L, m, m);
-    const long long srow = (long long)seedoff[m] + (wact ? (l0w - m) / kSeedStride : 0);
-    typename M::acc acc[2][CF];
+    const long long srow = (long long)seedoff[m] + (hact ? (lh - m) / kSeedStride : 0);
+    typename M::acc acc[NF][2][CF];
 #pragma unroll
-    for (int a = 0; a < 2; a++)
+    for (int f = 0; f < NF; f++)
 #pragma unroll
-        for (int c = 0; c < CF; c++) acc[a][c] = typename M::acc{};
+        for (int a = 0; a < 2; a++)
+#pragma unroll
+            for (int c = 0; c < CF; c++) acc[f][a][c] = typename M::acc{};
     const int colb = ct * sh.CT + i16;
-    const int nchunk = (npair + 63) / 64;
-    const int lblk_end = m + lt * kLTile + kLTile - 1;
+    const int nchunk = (npair + kAnalPC - 1) / kAnalPC;
+    const int lend = l0w + RW - 1;
     for (int pc = 0; pc < nchunk; pc++) {
-        // polar skip: every pair of the chunk has |lambda| < 1e-30 on these rows
         const int cm = cmin[(long long)m * nchunk + pc];
-        if (cm > lblk_end) continue;  // block-uniform
-        const bool wrows = wact && cm <= l0w + 31;  // wave-uniform
+        if (cm > lend) continue;  // wave-uniform
+        // first fragment with a row at or above cm
+        const int f0 = cm <= l0w + 31 ? 0 : (cm - l0w - 31 + 31) / 32;
         // B operands F_{E/O}[pair][column] of a K-step (4 pairs), loaded one step
-        // ahead; the first step's loads overlap the recurrence below.  Pairs
-        // past the last one read the next m (or the zero padding after the
-        // last m) and meet lambda = 0 exactly.
-        const T *fbase = F + ((long long)m * npair + pc * 64 + k4) * 2 * Cpad + colb;
-        T fE[CF], fO[CF], gE[CF], gO[CF];
+        // ahead; pairs past the last one read the next m (or the zero padding
+        // after the last m) and meet lambda = 0 exactly
+        const T *fbase = F + ((long long)m * npair + pc * kAnalPC + k4) * 2 * Cpad + colb;
+        T fE[CF], fO[CF], gE_[CF], gO_[CF];
         auto loadF = [&](int kk, T *E, T *O) {
             const T *f = fbase + (long long)(4 * kk) * 2 * Cpad;
 #pragma unroll
@@ -656,108 +759,121 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                 O[cf] = f[Cpad + 16 * cf];
             }
         };
-        if (wrows) loadF(0, fE, fO);
-        const int p = pc * 64 + lane;
-        const bool pv = wrows && p < npair;
-        double a1 = 0.0, a0 = 0.0, xp = 0.0;  // lambda_{l-1}, lambda_{l-2}
-        if (pv) {
-            const double2 sd = seed[srow * npair + p];
-            a1 = sd.x;
-            a0 = sd.y;
-            xp = x[p];
-        }
-        if (wrows) {
+        loadF(0, fE, fO);
+        {
+            const int p = pc * kAnalPC + pl;
+            const bool pv = hact && p < npair;
+            double a1 = 0.0, a0 = 0.0, xp = 0.0;  // lambda_{l-1}, lambda_{l-2}
+            if (pv) {
+                const double2 sd = seed[srow * npair + p];
+                a1 = sd.x;
+                a0 = sd.y;
+                xp = x[p];
+            }
 #pragma unroll 4
-            for (int q = 0; q < 32; q++) {
-                const int l = l0w + q;
+            for (int q = 0; q < RW / 2; q++) {
+                const int row = half * (RW / 2) + q;
+                const int l = l0w + row;
                 const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
                 const double v = ab.x * xp * a1 - ab.y * a0;
-                lam[wave][q][lane] = (T)v;
+                lam[row][pl] = (T)v;
                 a0 = a1;
                 a1 = v;
             }
         }
         __syncthreads();
-        // 16 K-steps in pairs, the operand buffers swapping roles
         auto kstep = [&](int kk, const T *E, const T *O) {
-            const T aE = lam[wave][2 * i16][4 * kk + k4];
-            const T aO = lam[wave][2 * i16 + 1][4 * kk + k4];
 #pragma unroll
-            for (int cf = 0; cf < CF; cf++) {
-                acc[0][cf] = M::mfma(aE, E[cf], acc[0][cf]);
-                acc[1][cf] = M::mfma(aO, O[cf], acc[1][cf]);
+            for (int f = 0; f < NF; f++) {
+                if (f >= f0) {
+                    const T aE = lam[2 * (16 * f + i16)][4 * kk + k4];
+                    const T aO = lam[2 * (16 * f + i16) + 1][4 * kk + k4];
+#pragma unroll
+                    for (int cf = 0; cf < CF; cf++) {
+                        acc[f][0][cf] = M::mfma(aE, E[cf], acc[f][0][cf]);
+                        acc[f][1][cf] = M::mfma(aO, O[cf], acc[f][1][cf]);
+                    }
+                }
             }
         };
-        for (int kk = 0; kk < (wrows ? 16 : 0); kk += 2) {
-            loadF(kk + 1, gE, gO);
+        // 8 K-steps in pairs, the operand buffers swapping roles
+        for (int kk = 0; kk < kAnalPC / 4; kk += 2) {
+            loadF(kk + 1, gE_, gO_);
             kstep(kk, fE, fO);
-            if (kk + 2 < 16) loadF(kk + 2, fE, fO);
-            kstep(kk + 1, gE, gO);
+            if (kk + 2 < kAnalPC / 4) loadF(kk + 2, fE, fO);
+            kstep(kk + 1, gE_, gO_);
         }
         __syncthreads();
     }
 
     const int Npad = Cpad / 2;
 #pragma unroll
-    for (int par = 0; par < 2; par++)
+    for (int f = 0; f < NF; f++)
 #pragma unroll
-        for (int r = 0; r < 4; r++) {
-            const int l = l0w + 2 * M::row(k4, r) + par;
-            const bool lok = wact && l <= L;
-            double sT = 0.0, sE = 0.0;
+        for (int par = 0; par < 2; par++)
 #pragma unroll
-            for (int cf = 0; cf < CF; cf++) {
-                const int col = colb + 16 * cf;
-                const int s = col >> 1;
-                double v = (double)acc[par][cf][r];
-                if (MODE == 2) {
-                    if (lok) {
-                        const long long id = lm_index(l, m);
-                        const double2 t = gT[id], e = gE[id];
-                        const double wt = W[(long long)l * Npad + s];
-                        const double we = W[(long long)(L + 1 + l) * Npad + s];
-                        v += (col & 1) ? (m == 0 ? 0.0 : wt * t.y + we * e.y) : wt * t.x + we * e.x;
-                        if (m == 0 && (col & 1)) v = 0.0;
+            for (int r = 0; r < 4; r++) {
+                const int l = l0w + 2 * (16 * f + M::row(k4, r)) + par;
+                const bool lok = l <= L;
+                double sT = 0.0, sE = 0.0;
+#pragma unroll
+                for (int cf = 0; cf < CF; cf++) {
+                    const int col = colb + 16 * cf;
+                    const int s = col >> 1;
+                    double v = (double)acc[f][par][cf][r];
+                    if (MODE == 2) {
+                        if (lok) {
+                            const long long id = lm_index(l, m);
+                            const double2 t = gT[id], e = gE[id];
+                            const double wt = W[(long long)l * Npad + s];
+                            const double we = W[(long long)(L + 1 + l) * Npad + s];
+                            v += (col & 1) ? (m == 0 ? 0.0 : wt * t.y + we * e.y)
+                                           : wt * t.x + we * e.x;
+                            if (m == 0 && (col & 1)) v = 0.0;
+                            outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
+                        }
+                        continue;
+                    }
+                    if (m == 0 && l == 0) {
+                        if (sh.mean_mode == 0)
+                            v = 0.0;
+                        else if ((col & 1) == 0)
+                            v -= mu[s];
+                    }
+                    if (MODE == 0) {
+                        if (lok) {
+                            sT += W[(long long)l * Npad + s] * v;
+                            sE += W[(long long)(L + 1 + l) * Npad + s] * v;
+                        }
+                    } else if (lok) {
                         outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
                     }
-                    continue;
-                }
-                if (m == 0 && l == 0) {
-                    if (sh.mean_mode == 0)
-                        v = 0.0;
-                    else if ((col & 1) == 0)
-                        v -= mu[s];
                 }
                 if (MODE == 0) {
-                    if (lok) {
-                        sT += W[(long long)l * Npad + s] * v;
-                        sE += W[(long long)(L + 1 + l) * Npad + s] * v;
+                    sT += __shfl_xor(sT, 2);
+                    sT += __shfl_xor(sT, 4);
+                    sT += __shfl_xor(sT, 8);
+                    sE += __shfl_xor(sE, 2);
+                    sE += __shfl_xor(sE, 4);
+                    sE += __shfl_xor(sE, 8);
+                    if (lok && i16 < 2) {
+                        const long long id = lm_index(l, m);
+                        double *pT =
+                            reinterpret_cast<double *>(part + ((long long)ct * 2) * sh.nlm + id);
+                        double *pE =
+                            reinterpret_cast<double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
+                        pT[i16] = (m == 0 && i16 == 1) ? 0.0 : sT;
+                        pE[i16] = (m == 0 && i16 == 1) ? 0.0 : sE;
                     }
-                } else if (lok) {
-                    outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
                 }
             }
-            if (MODE == 0) {
-                sT += __shfl_xor(sT, 2);
-                sT += __shfl_xor(sT, 4);
-                sT += __shfl_xor(sT, 8);
-                sE += __shfl_xor(sE, 2);
-                sE += __shfl_xor(sE, 4);
-                sE += __shfl_xor(sE, 8);
-                if (lok && i16 < 2) {
-                    const long long id = lm_index(l, m);
-                    double *pT = reinterpret_cast<double *>(part + ((long long)ct * 2) * sh.nlm + id);
-                    double *pE =
-                        reinterpret_cast<double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
-                    pT[i16] = (m == 0 && i16 == 1) ? 0.0 : sT;
-                    pE[i16] = (m == 0 && i16 == 1) ? 0.0 : sE;
-                }
-            }
-        }
 }
 
+// waves per SIMD the analysis register budget is held to
+template <typename T> constexpr int anal_waves() { return 2; }
+
 template <typename T, int CF, int MODE>
-__global__ __launch_bounds__(256) void k_anal(Shape sh, const int4 *__restrict__ tiles,
+__global__ __launch_bounds__(64, anal_waves<T>()) void k_anal(Shape sh, const int4 *__restrict__ tiles,
                                               const double *__restrict__ x,
                                               const double2 *__restrict__ coef,
                                               const double2 *__restrict__ seed,
@@ -890,7 +1006,7 @@ __global__ __launch_bounds__(256) void g_ring(const GroupItem *__restrict__ it,
 }
 
 template <typename T, int CF>
-__global__ __launch_bounds__(256) void g_anal(const GroupItem *__restrict__ it,
+__global__ __launch_bounds__(64, anal_waves<T>()) void g_anal(const GroupItem *__restrict__ it,
                                               const int *__restrict__ ord,
                                               const int *__restrict__ off, int n)
 {
@@ -949,12 +1065,12 @@ __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__res
 __global__ __launch_bounds__(256) void k_chunk_min(Shape sh, const int *__restrict__ lstart,
                                                    int *__restrict__ cmin)
 {
-    const int nchunk = (sh.npair + 63) / 64;
+    const int nchunk = (sh.npair + kAnalPC - 1) / kAnalPC;
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (long long)(sh.L + 1) * nchunk) return;
     const int c = (int)(t % nchunk), m = (int)(t / nchunk);
     int v = sh.L + 1;
-    for (int p = c * 64; p < min(sh.npair, c * 64 + 64); p++)
+    for (int p = c * kAnalPC; p < min(sh.npair, c * kAnalPC + kAnalPC); p++)
         v = min(v, lstart[(long long)m * sh.npair + p]);
     cmin[t] = v;
 }
@@ -1258,7 +1374,7 @@ hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s)
     const long long n = (long long)(sh.L + 1) * sh.npair;
     hipLaunchKernelGGL(k_seed_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, sh, b.x, b.lmm,
                        b.coef, b.seedoff, b.seed, b.lstart);
-    const long long nc = (long long)(sh.L + 1) * ((sh.npair + 63) / 64);
+    const long long nc = (long long)(sh.L + 1) * ((sh.npair + kAnalPC - 1) / kAnalPC);
     hipLaunchKernelGGL(k_chunk_min, dim3(blocks_for(nc, 256)), dim3(256), 0, s, sh, b.lstart,
                        b.cmin);
     return hipGetLastError();
@@ -1363,15 +1479,15 @@ static void anal_t(const Shape &sh, const Bufs &b, const void *F, void *out, int
 {
     dim3 grid(b.nk4);
     if (mode == 0)
-        hipLaunchKernelGGL((k_anal<T, CF, 0>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
+        hipLaunchKernelGGL((k_anal<T, CF, 0>), grid, dim3(64), 0, s, sh, b.k4tiles, b.x, b.coef,
                            b.seed, b.seedoff, b.cmin, b.W, b.mu, (const T *)F, b.part,
                            (T *)out, gT, gE);
     else if (mode == 1)
-        hipLaunchKernelGGL((k_anal<T, CF, 1>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
+        hipLaunchKernelGGL((k_anal<T, CF, 1>), grid, dim3(64), 0, s, sh, b.k4tiles, b.x, b.coef,
                            b.seed, b.seedoff, b.cmin, b.W, b.mu, (const T *)F, b.part,
                            (T *)out, gT, gE);
     else
-        hipLaunchKernelGGL((k_anal<T, CF, 2>), grid, dim3(256), 0, s, sh, b.k4tiles, b.x, b.coef,
+        hipLaunchKernelGGL((k_anal<T, CF, 2>), grid, dim3(64), 0, s, sh, b.k4tiles, b.x, b.coef,
                            b.seed, b.seedoff, b.cmin, b.W, b.mu, (const T *)F, b.part,
                            (T *)out, gT, gE);
 }
@@ -1517,7 +1633,7 @@ static void group_cf(int stage, const GroupItem *it, const int *ord, const int *
     if (stage == GS_SYNTH)
         hipLaunchKernelGGL((g_synth<T, CF>), grid, dim3(64), 0, s, it, ord, off, n);
     else
-        hipLaunchKernelGGL((g_anal<T, CF>), grid, dim3(256), 0, s, it, ord, off, n);
+        hipLaunchKernelGGL((g_anal<T, CF>), grid, dim3(64), 0, s, it, ord, off, n);
 }
 
 template <typename T>
