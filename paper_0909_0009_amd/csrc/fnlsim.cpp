@@ -391,7 +391,7 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
         const double st = std::sqrt((1.0 - xp[p]) * (1.0 + xp[p]));
         for (int m = 0; m <= L; m++) lmm[(size_t)m * np + p] = lambda_mm(m, st);
     }
-    std::vector<double2> coef(sh.nlm);
+    std::vector<double2> coef(sh.nlm + (size_t)(L + 1) * fnl::kCoefPad, make_double2(0.0, 0.0));
     for (int m = 0; m <= L; m++)
         for (int l = m; l <= L; l++) {
             double A = 0.0, B = -1.0;
@@ -400,7 +400,7 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
                 A = std::sqrt((4.0 * l2 - 1.0) / (l2 - m2));
                 B = A * std::sqrt((lp * lp - m2) / (4.0 * lp * lp - 1.0));
             }
-            coef[fnl::mrow(L, m, l)] = make_double2(A, B);
+            coef[fnl::crow(L, m) + (l - m)] = make_double2(A, B);
         }
     const int Npad = sh.Cpad / 2;
     std::vector<double> W((size_t)2 * (L + 1) * Npad, 0.0);

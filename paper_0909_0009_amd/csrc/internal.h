@@ -12,6 +12,7 @@ constexpr int kMaxPhi = 8192;   // longest ring the in-LDS FFT handles
 constexpr int kMaxPasses = 16;
 constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
 constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)
+constexpr int kCoefPad = 128;      // zero rows after each m's coefficient block (>= analysis rows per block)
 
 // Everything a kernel needs to know about the problem's shape.
 struct Shape {
@@ -40,6 +41,11 @@ struct Shape {
 __host__ __device__ inline long long mrow(int L, int m, int l) {
     return (long long)m * (L + 1) - (long long)m * (m - 1) / 2 + (l - m);
 }
+// First row of m's block in the padded coefficient table: rows l = m..L,
+// then kCoefPad zero rows.
+__host__ __device__ inline long long crow(int L, int m) {
+    return mrow(L, m, m) + (long long)m * kCoefPad;
+}
 __host__ __device__ inline long long lm_index(int l, int m) {
     return (long long)l * (l + 1) / 2 + m;
 }
@@ -53,7 +59,8 @@ struct Bufs {
     double *x;         // [npair] cos theta of the north ring of each pair
     double *wq;        // [npair] omega_p * 2 pi / nphi
     double *lmm;       // [L+1][npair] lambda_mm(x_p)
-    double2 *coef;     // [nlm] (A, B): lambda_l = A x lambda_{l-1} - B lambda_{l-2}
+    double2 *coef;     // [nlm + (L+1) kCoefPad] (A, B): lambda_l = A x lambda_{l-1} - B lambda_{l-2},
+                       // m-major blocks (crow) each followed by kCoefPad zero rows
     double2 *seed;     // [nseedrow][npair] recurrence state (lambda_{l0-1}, lambda_{l0-2})
                        // entering l0 = m + 32u ((0, lambda_mm) for u = 0)
     int *seedoff;      // [L+2] first seed row of each m

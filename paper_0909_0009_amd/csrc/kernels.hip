@@ -198,7 +198,11 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int4 tl = tiles[bid];
     if (tl.x < 0) return;  // idle slot of the XCD layout
-    const int m = tl.x, pt = tl.y, ct = tl.z;
+    // wave-uniform: keeps the coefficient addresses scalar
+    const int m = __builtin_amdgcn_readfirstlane(tl.x);
+    const int pt = __builtin_amdgcn_readfirstlane(tl.y);
+    const int ct = __builtin_amdgcn_readfirstlane(tl.z);
+    const double2 *__restrict__ cm_row = coef + crow(L, m);
     const int lane = threadIdx.x;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int p0 = pt * PW;
@@ -209,6 +213,8 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
     int ls = pv ? lstart[(long long)m * npair + p] : L + 1;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) ls = min(ls, __shfl_xor(ls, o));
+    // uniform after the reduction: lets the coefficient loads go scalar
+    ls = __builtin_amdgcn_readfirstlane(ls);
     const int u0 = ls <= L ? (ls - m) / kSeedStride : 0;
     double l1 = 0.0, l2 = 0.0;
     if (pv && ls <= L) {
@@ -244,7 +250,9 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
 #pragma unroll
         for (int q = 0; q < 8; q++) {
             const int l = l0 + q;
-            const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
+            // rows past L are the zero padding of m's coefficient block, so
+            // lambda = 0 there exactly
+            const double2 ab = cm_row[l - m];
             const double nv = ab.x * xp * l1 - ab.y * l2;
             v[q] = nv;
             l2 = l1;
@@ -688,6 +696,7 @@ __global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict
 template <typename T> constexpr int anal_rw() { return sizeof(T) == 8 ? 64 : 128; }
 template <typename T> constexpr int anal_ld() { return sizeof(T) == 8 ? 33 : 34; }
 constexpr int kAnalPC = 32;
+static_assert(kCoefPad >= anal_rw<float>() && kCoefPad >= anal_rw<double>(), "coefficient padding");
 
 // Block = (m, RW l rows from l0 = m + RW t, column tile), one wave.  Rows with
 // l - m even meet F_E, odd ones F_O: NF = RW/32 fragments of 16 rows per
@@ -722,7 +731,11 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int4 tl = tiles[bid];
     if (tl.x < 0) return;  // idle slot of the XCD layout
-    const int m = tl.x, lt = tl.y, ct = tl.z;
+    // wave-uniform: keeps the coefficient addresses scalar
+    const int m = __builtin_amdgcn_readfirstlane(tl.x);
+    const int lt = __builtin_amdgcn_readfirstlane(tl.y);
+    const int ct = __builtin_amdgcn_readfirstlane(tl.z);
+    const double2 *__restrict__ cm_row = coef + crow(L, m);
     const int lane = threadIdx.x;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int half = lane >> 5, pl = lane & 31;
@@ -770,13 +783,16 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                 a0 = sd.y;
                 xp = x[p];
             }
+            // the coefficient rows of both halves have wave-uniform addresses
+            // (scalar loads); each lane keeps its half's
 #pragma unroll 4
             for (int q = 0; q < RW / 2; q++) {
-                const int row = half * (RW / 2) + q;
-                const int l = l0w + row;
-                const double2 ab = (l <= L) ? coef[rowm + (l - m)] : make_double2(0.0, 0.0);
+                const int lA = l0w + q, lB = l0w + RW / 2 + q;
+                // rows past l = L read the zero padding of m's block
+                const double2 cA = cm_row[lA - m], cB = cm_row[lB - m];
+                const double2 ab = half ? cB : cA;
                 const double v = ab.x * xp * a1 - ab.y * a0;
-                lam[row][pl] = (T)v;
+                lam[half * (RW / 2) + q][pl] = (T)v;
                 a0 = a1;
                 a1 = v;
             }
@@ -1047,13 +1063,12 @@ __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__res
     const int p = (int)(t % npair), m = (int)(t / npair);
     const double xp = x[p];
     double l1 = 0.0, l2 = lmm[(long long)m * npair + p];
-    const long long rowm = mrow(L, m, m);
     int first = L + 1;
     for (int l = m; l <= L; l++) {
         const int d = l - m;
         if (d % kSeedStride == 0)
             seed[((long long)seedoff[m] + d / kSeedStride) * npair + p] = make_double2(l1, l2);
-        const double2 ab = coef[rowm + d];
+        const double2 ab = coef[crow(L, m) + d];
         const double v = ab.x * xp * l1 - ab.y * l2;
         if (first > L && fabs(v) > kLambdaTiny) first = l;
         l2 = l1;
