@@ -276,8 +276,9 @@ int build_precision_tables(sim_ctx *c, const double *filter)
     rc = upload(c, &b.tw, tw.data(), tw.size());
     if (rc) return rc;
     const size_t elem = sizeof(T);
-    // 8 zero rows past the last m block: the synthesis reads whole K-steps
-    const size_t phib = elem * ((size_t)sh.nlm + 8) * sh.Cpad;
+    // zero rows past the last m block: the synthesis reads whole K-steps and
+    // prefetches two K-steps ahead
+    const size_t phib = elem * ((size_t)sh.nlm + fnl::kPhiPad) * sh.Cpad;
     if ((rc = alloc_zero(c, &b.phi, phib))) return rc;
     if ((rc = alloc_zero(c, &b.scratch, phib))) return rc;
     const size_t gb = elem * (size_t)sh.npair * (L + 1) * 2 * sh.Cpad;

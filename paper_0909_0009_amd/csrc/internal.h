@@ -13,6 +13,7 @@ constexpr int kMaxPasses = 16;
 constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
 constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)
 constexpr int kCoefPad = 128;      // zero rows after each m's coefficient block (>= analysis rows per block)
+constexpr int kPhiPad = 32;        // zero rows after the last m block of the Phi matrices (synthesis prefetch)
 
 // Everything a kernel needs to know about the problem's shape.
 struct Shape {

@@ -13,6 +13,8 @@
 //                       MFMA with the recurrence transposed through LDS, and the
 //                       radial sum with W^X_ls in the epilogue
 //   k_combine     a = a_L + f_NL a_NL with a compensated sum over column tiles
+#include <type_traits>
+
 #include "internal.h"
 
 namespace fnl {
@@ -244,52 +246,63 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
             O[cf] = rE[Cpad + 16 * cf];
         }
     };
-    int buf = 0;
-    auto kstep = [&](int l0, const T *E, const T *O) {
-        double v[8];
+    // FULL: every fragment holds a pair (all tiles but the last), so the
+    // K-step has no branches between its LDS reads and MFMAs
+    auto run = [&](auto full) {
+        constexpr bool FULL = decltype(full)::value;
+        int buf = 0;
+        auto kstep = [&](int l0, const T *E, const T *O) {
+            double v[8];
 #pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int l = l0 + q;
-            // rows past L are the zero padding of m's coefficient block, so
-            // lambda = 0 there exactly
-            const double2 ab = cm_row[l - m];
-            const double nv = ab.x * xp * l1 - ab.y * l2;
-            v[q] = nv;
-            l2 = l1;
-            l1 = nv;
-        }
-        if (lane < PW) {
+            for (int q = 0; q < 8; q++) {
+                // rows past L are the zero padding of m's coefficient block, so
+                // lambda = 0 there exactly
+                const double2 ab = cm_row[l0 + q - m];
+                const double nv = ab.x * xp * l1 - ab.y * l2;
+                v[q] = nv;
+                l2 = l1;
+                l1 = nv;
+            }
+            if (PW == 64 || lane < PW) {
 #pragma unroll
-            for (int q = 0; q < 8; q++) lamT[buf][q][lane] = (T)v[q];
-        }
-        __syncthreads();  // one wave: orders the tile writes before the reads
+                for (int q = 0; q < 8; q++) lamT[buf][q][lane] = (T)v[q];
+            }
+            __syncthreads();  // one wave: orders the tile writes before the reads
 #pragma unroll
-        for (int f = 0; f < NF; f++) {
-            if (f < nfa) {
-                const T aE = lamT[buf][2 * k4][16 * f + i16];
-                const T aO = lamT[buf][2 * k4 + 1][16 * f + i16];
+            for (int f = 0; f < NF; f++) {
+                if (FULL || f < nfa) {
+                    const T aE = lamT[buf][2 * k4][16 * f + i16];
+                    const T aO = lamT[buf][2 * k4 + 1][16 * f + i16];
 #pragma unroll
-                for (int cf = 0; cf < CF; cf++) {
-                    acc[f][0][cf] = M::mfma(aE, E[cf], acc[f][0][cf]);
-                    acc[f][1][cf] = M::mfma(aO, O[cf], acc[f][1][cf]);
+                    for (int cf = 0; cf < CF; cf++) {
+                        acc[f][0][cf] = M::mfma(aE, E[cf], acc[f][0][cf]);
+                        acc[f][1][cf] = M::mfma(aO, O[cf], acc[f][1][cf]);
+                    }
                 }
             }
+            buf ^= 1;
+        };
+        // two K-steps per trip with the operand buffers swapping roles; the
+        // prefetch is unconditional (it may read up to 15 rows past the last m
+        // block, which is zero padding) so no wait has to cover a load that
+        // might not have been issued
+        T bE[CF], bO[CF], nE[CF], nO[CF];
+        const int nks = lbeg <= L ? (L - lbeg) / 8 + 1 : 0;
+        int l0 = lbeg;
+        if (nks > 0) loadB(l0, bE, bO);
+        for (int it = 0; it < nks / 2; it++) {
+            loadB(l0 + 8, nE, nO);
+            kstep(l0, bE, bO);
+            loadB(l0 + 16, bE, bO);
+            kstep(l0 + 8, nE, nO);
+            l0 += 16;
         }
-        buf ^= 1;
+        if (nks & 1) kstep(l0, bE, bO);
     };
-    // two K-steps per trip with the operand buffers swapping roles
-    T bE[CF], bO[CF], nE[CF], nO[CF];
-    const int nks = lbeg <= L ? (L - lbeg) / 8 + 1 : 0;
-    int l0 = lbeg;
-    if (nks > 0) loadB(l0, bE, bO);
-    for (int it = 0; it < nks / 2; it++) {
-        loadB(l0 + 8, nE, nO);
-        kstep(l0, bE, bO);
-        if (2 * it + 2 < nks) loadB(l0 + 16, bE, bO);
-        kstep(l0 + 8, nE, nO);
-        l0 += 16;
-    }
-    if (nks & 1) kstep(l0, bE, bO);
+    if (nfa == NF)
+        run(std::true_type{});
+    else
+        run(std::false_type{});
 #pragma unroll
     for (int f = 0; f < NF; f++)
 #pragma unroll
@@ -754,6 +767,8 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     const int colb = ct * sh.CT + i16;
     const int nchunk = (npair + kAnalPC - 1) / kAnalPC;
     const int lend = l0w + RW - 1;
+    // fragments holding a row l <= L (fragment f covers rows l0w + 32 f ..)
+    const int fend = min(NF, (L - l0w) / 32 + 1);
     for (int pc = 0; pc < nchunk; pc++) {
         const int cm = cmin[(long long)m * nchunk + pc];
         if (cm > lend) continue;  // wave-uniform
@@ -801,7 +816,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
         auto kstep = [&](int kk, const T *E, const T *O) {
 #pragma unroll
             for (int f = 0; f < NF; f++) {
-                if (f >= f0) {
+                if (f >= f0 && f < fend) {
                     const T aE = lam[2 * (16 * f + i16)][4 * kk + k4];
                     const T aO = lam[2 * (16 * f + i16) + 1][4 * kk + k4];
 #pragma unroll
@@ -812,11 +827,15 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                 }
             }
         };
-        // 8 K-steps in pairs, the operand buffers swapping roles
+        // 8 K-steps in pairs, the operand buffers swapping roles; the last
+        // prefetch (first K-step of the next chunk, or the zero padding after
+        // the last pair) is issued unconditionally so that every wait counts
+        // the same loads
+#pragma unroll 1
         for (int kk = 0; kk < kAnalPC / 4; kk += 2) {
             loadF(kk + 1, gE_, gO_);
             kstep(kk, fE, fO);
-            if (kk + 2 < kAnalPC / 4) loadF(kk + 2, fE, fO);
+            loadF(kk + 2, fE, fO);
             kstep(kk + 1, gE_, gO_);
         }
         __syncthreads();
