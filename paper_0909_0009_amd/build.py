@@ -48,7 +48,8 @@ def build(verbose=False, jobs=2):
             print(err, file=sys.stderr)
         if p.returncode != 0:
             raise RuntimeError(f"hipcc failed on {src}")
-    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    # -z defs: a symbol missing from the library fails the build, not the first load
+    link = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-Wl,-z,defs", "-o", LIB + ".tmp"] + objs
     if verbose:
         print(" ".join(link), flush=True)
     subprocess.check_call(link)

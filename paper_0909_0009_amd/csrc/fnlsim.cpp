@@ -59,7 +59,7 @@ struct sim_batch {
     int *plan_dev = nullptr;               // ord/off arrays of every launch
     struct Launch {
         int stage, CF, n, nblocks;
-        size_t lds;
+        int ring_n;                        // longest ring of the group (ring stage)
         int ord_off, off_off;              // offsets into plan_dev
     };
     std::vector<Launch> launches;
@@ -693,6 +693,13 @@ int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const 
 {
     if (!c) return SIM_EINVAL;
     if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    {
+        // the reverse ring stage holds two rings of the grid in LDS
+        const size_t elem = c->sh.fp32 ? sizeof(float2) : sizeof(double2);
+        if (2 * elem * (size_t)fnl::ring_pad(c->sh.nphi) > fnl::kMaxLds)
+            return fail(c, SIM_EINVAL, "n_phi %d is too long for the reverse pass at this precision",
+                        c->sh.nphi);
+    }
     if (!noise || !fnl || !gT || !gE || !grad_n || !grad_fnl)
         return fail(c, SIM_EINVAL, "a required pointer is NULL");
     for (int r = 0; r < R; r++)
@@ -818,16 +825,16 @@ int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
         for (int m : members) plan.push_back(m);
         l.off_off = (int)plan.size();
         long long acc = 0;
-        size_t lds = 0;
+        int ring_n = 0;
         for (int m : members) {
             plan.push_back((int)acc);
             const sim_ctx *c = ctxs[m];
             acc += (fnl::group_blocks(stage, c->sh, c->b) + 7) / 8 * 8;
-            lds = std::max(lds, (c->sh.fp32 ? sizeof(float2) : sizeof(double2)) * (size_t)c->sh.nphi);
+            ring_n = std::max(ring_n, c->sh.nphi);
         }
         plan.push_back((int)acc);
         l.nblocks = (int)acc;
-        l.lds = stage == fnl::GS_RING ? lds : 0;
+        l.ring_n = stage == fnl::GS_RING ? ring_n : 0;
         b->launches.push_back(l);
     };
     for (int stage = 0; stage < fnl::GS_COUNT; stage++) {
@@ -838,6 +845,19 @@ int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
                     if (ctxs[i]->sh.CF == cf) mem.push_back(i);
                 add_launch(stage, cf, mem);
             }
+        } else if (stage == fnl::GS_RING) {
+            // one launch per register bucket and FFT kind (CF = 1: every ring
+            // length of the launch has a compile-time plan)
+            for (int bucket : {8192, 4096, 2048, 1024})
+                for (int planned = 1; planned >= 0; planned--) {
+                    std::vector<int> mem;
+                    for (int i : order) {
+                        const int n = ctxs[i]->sh.nphi;
+                        if (fnl::ring_bucket(n) == bucket && (int)fnl::fft_has_plan(n) == planned)
+                            mem.push_back(i);
+                    }
+                    add_launch(stage, planned, mem);
+                }
         } else {
             add_launch(stage, 0, order);
         }
@@ -858,7 +878,7 @@ int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
         return rc;
     }
     for (const auto &l : b->launches)
-        if (l.stage == fnl::GS_RING && (e = fnl::prepare_group_ring(b->fp32, l.lds)) != hipSuccess) {
+        if (l.stage == fnl::GS_RING && (e = fnl::prepare_group_ring(b->fp32, l.ring_n, l.CF)) != hipSuccess) {
             const int rc = batch_fail(b, SIM_EDEVICE, "batch ring LDS", e);
             sim_batch_destroy(b);
             return rc;
@@ -878,7 +898,7 @@ static hipError_t batch_launch_all(sim_batch *b, hipStream_t s)
     for (const auto &l : b->launches) {
         const hipError_t e = fnl::launch_group(l.stage, b->fp32, l.CF, b->items_dev,
                                                b->plan_dev + l.ord_off, b->plan_dev + l.off_off,
-                                               l.n, l.nblocks, l.lds, s);
+                                               l.n, l.nblocks, (size_t)l.ring_n, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;

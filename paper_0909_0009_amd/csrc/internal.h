@@ -37,6 +37,24 @@ struct Shape {
     int lower;    // 1 if every F_l is lower triangular (contractions stop at the diagonal)
 };
 
+// Elements of one ring buffer in LDS: n values at j + j/32, plus one slot.
+__host__ __device__ constexpr int ring_pad(int n) { return n + (n >> 5) + 1; }
+constexpr size_t kMaxLds = 163840;  // LDS bytes a workgroup may allocate
+// Shells per forward ring block (256 threads each) in FP32 / FP64.
+constexpr int kRingShellsF32 = 2;
+constexpr int kRingShellsF64 = 1;
+inline int ring_shells(int fp32) { return fp32 ? kRingShellsF32 : kRingShellsF64; }
+// Ring lengths the FFT has a compile-time plan for (all other 5-smooth
+// lengths take the run-time plan), and the register bucket of a length.
+__host__ __device__ constexpr bool fft_has_plan(int n)
+{
+    return n == 768 || n == 1024 || n == 1536 || n == 3072 || n == 6144;
+}
+__host__ __device__ constexpr int ring_bucket(int n)
+{
+    return n <= 1024 ? 1024 : n <= 2048 ? 2048 : n <= 4096 ? 4096 : 8192;
+}
+
 // Row of coefficient (l, m) in the m-major layouts: rows of one m are
 // contiguous, m ascending.
 __host__ __device__ inline long long mrow(int L, int m, int l) {
@@ -111,7 +129,7 @@ long long group_blocks(int stage, const Shape &sh, const Bufs &b);
 hipError_t launch_group(int stage, int fp32, int CF, const GroupItem *items, const int *ord,
                         const int *off, int n, int nblocks, size_t lds, hipStream_t s);
 // Raise the dynamic-LDS limit of the grouped ring kernel (call before capture).
-hipError_t prepare_group_ring(int fp32, size_t lds);
+hipError_t prepare_group_ring(int fp32, int nphi, int planned);
 
 // ----- launchers (kernels.hip); all asynchronous on `s`.
 hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);  // seeds, lstart, cmin

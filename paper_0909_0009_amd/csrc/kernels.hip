@@ -30,6 +30,8 @@ template <typename T> struct Mt;
 template <> struct Mt<double> {
     using acc = v4d;
     using c2 = double2;
+    using c2v = double2;
+    using quad = double4;
     __device__ static inline acc mfma(double a, double b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
     }
@@ -38,6 +40,8 @@ template <> struct Mt<double> {
 template <> struct Mt<float> {
     using acc = v4f;
     using c2 = float2;
+    using c2v = float2;
+    using quad = float4;
     __device__ static inline acc mfma(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
@@ -303,19 +307,23 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
         run(std::true_type{});
     else
         run(std::false_type{});
+    // G[pair][m][column] holds (E, O) interleaved
+    using C2V = typename M::c2v;
 #pragma unroll
     for (int f = 0; f < NF; f++)
 #pragma unroll
-        for (int par = 0; par < 2; par++)
+        for (int cf = 0; cf < CF; cf++)
 #pragma unroll
-            for (int cf = 0; cf < CF; cf++)
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const int pair = p0 + 16 * f + M::row(k4, r);
-                    if (pair < npair)
-                        G[(((long long)pair * (L + 1) + m) * 2 + par) * Cpad + colb + 16 * cf] =
-                            acc[f][par][cf][r];
+            for (int r = 0; r < 4; r++) {
+                const int pair = p0 + 16 * f + M::row(k4, r);
+                if (pair < npair) {
+                    C2V v;
+                    v.x = acc[f][0][cf][r];
+                    v.y = acc[f][1][cf][r];
+                    *reinterpret_cast<C2V *>(
+                        G + ((((long long)pair * (L + 1) + m) * Cpad) + colb + 16 * cf) * 2) = v;
                 }
+            }
 }
 
 // waves per SIMD the synthesis register budget is held to
@@ -367,8 +375,124 @@ template <typename C2> __device__ inline C2 cmuli(C2 a, int s)
     return r;
 }
 
+// cos and sin of 2 pi j / R, evaluated at compile time: quarter-turn
+// reduction to |x| <= pi/4, then Taylor series (terms beyond x^27 are below
+// double rounding there).
+constexpr double ct_sin_red(double x)
+{
+    double t = x, s = x;
+    for (int k = 1; k < 14; k++) {
+        t *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+        s += t;
+    }
+    return s;
+}
+constexpr double ct_cos_red(double x)
+{
+    double t = 1.0, s = 1.0;
+    for (int k = 1; k < 14; k++) {
+        t *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+        s += t;
+    }
+    return s;
+}
+// angle 2 pi j / R = q pi/2 + x with q = round(4 j / R)
+constexpr int ct_quad(int j, int R) { return ((8 * j + R) / (2 * R)) & 3; }
+constexpr double ct_rem(int j, int R)
+{
+    const int q = (8 * j + R) / (2 * R);
+    return 6.28318530717958647692 * (double)(4 * j - q * R) / (4.0 * R);
+}
+constexpr double ct_cos(int j, int R)
+{
+    const int q = ct_quad(j, R);
+    const double x = ct_rem(j, R);
+    return q == 0 ? ct_cos_red(x) : q == 1 ? -ct_sin_red(x) : q == 2 ? -ct_cos_red(x) : ct_sin_red(x);
+}
+constexpr double ct_sin(int j, int R)
+{
+    const int q = ct_quad(j, R);
+    const double x = ct_rem(j, R);
+    return q == 0 ? ct_sin_red(x) : q == 1 ? ct_cos_red(x) : q == 2 ? -ct_sin_red(x) : -ct_cos_red(x);
+}
+
+// v * e^{sg 2 pi i J / R} (sg = +1 for INV, -1 otherwise) with the trivial
+// and eighth-turn factors done without a full complex product.
+template <typename C2, int J, int R, bool INV> __device__ __forceinline__ C2 ctwist(C2 v)
+{
+    using T = decltype(v.x);
+    constexpr int sg = INV ? 1 : -1;
+    constexpr int j = J % R;
+    if constexpr (j == 0) {
+        return v;
+    } else if constexpr ((4 * j) % R == 0) {
+        constexpr int q = (4 * j) / R;  // quarter turns
+        if constexpr (q == 2) {
+            C2 r;
+            r.x = -v.x;
+            r.y = -v.y;
+            return r;
+        } else {
+            return cmuli(v, q == 1 ? sg : -sg);
+        }
+    } else if constexpr ((8 * j) % R == 0) {
+        constexpr double c = ct_cos(j, R), sn = sg * ct_sin(j, R);
+        constexpr double h = 0.70710678118654752440;
+        // (c + i sn) with |c| = |sn| = sqrt(1/2)
+        const T a = (T)(c > 0 ? h : -h), b = (T)(sn > 0 ? h : -h);
+        C2 r;
+        r.x = a * v.x - b * v.y;
+        r.y = a * v.y + b * v.x;
+        return r;
+    } else {
+        constexpr double c = ct_cos(j, R), sn = sg * ct_sin(j, R);
+        C2 r;
+        r.x = (T)c * v.x - (T)sn * v.y;
+        r.y = (T)c * v.y + (T)sn * v.x;
+        return r;
+    }
+}
+
+template <typename C2, int R, bool INV> __device__ __forceinline__ void dft_small(C2 *a);
+
+// y[n2][k1] *= w_{R1 R2}^{n2 k1} for every entry, each with its constant factor
+template <typename C2, int R1, int R2, bool INV, int I>
+__device__ __forceinline__ void twist_all(C2 (&y)[R2][R1])
+{
+    if constexpr (I < R1 * R2) {
+        y[I / R1][I % R1] = ctwist<C2, (I / R1) * (I % R1), R1 * R2, INV>(y[I / R1][I % R1]);
+        twist_all<C2, R1, R2, INV, I + 1>(y);
+    }
+}
+
+// DFT of length R1 R2 from R2 DFTs of length R1, twiddles, and R1 DFTs of
+// length R2: input n = R2 n1 + n2, output k = k1 + R1 k2.
+template <typename C2, int R1, int R2, bool INV> __device__ __forceinline__ void dft_comp(C2 *a)
+{
+    C2 y[R2][R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; n2++) {
+        C2 t[R1];
+#pragma unroll
+        for (int n1 = 0; n1 < R1; n1++) t[n1] = a[R2 * n1 + n2];
+        dft_small<C2, R1, INV>(t);
+#pragma unroll
+        for (int k1 = 0; k1 < R1; k1++) y[n2][k1] = t[k1];
+    }
+    twist_all<C2, R1, R2, INV, 0>(y);  // y[n2][k1] *= w_R^{n2 k1}
+#pragma unroll
+    for (int k1 = 0; k1 < R1; k1++) {
+        C2 t[R2];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; n2++) t[n2] = y[n2][k1];
+        dft_small<C2, R2, INV>(t);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; k2++) a[k1 + R1 * k2] = t[k2];
+    }
+}
+
 // Radix-R DFT in place; forward uses e^{-2 pi i t k / R}, INV e^{+...}.
-template <typename C2, int R, bool INV> __device__ inline void dft_small(C2 *a)
+template <typename C2, int R, bool INV> __device__ __forceinline__ void dft_small(C2 *a)
 {
     using T = decltype(a[0].x);
     constexpr int sg = INV ? 1 : -1;  // sign of the exponent
@@ -395,7 +519,16 @@ template <typename C2, int R, bool INV> __device__ inline void dft_small(C2 *a)
         a[2] = csub(t0, t2);
         a[1] = cadd(t1, cmuli(t3, sg));
         a[3] = csub(t1, cmuli(t3, sg));
+    } else if constexpr (R == 6) {
+        dft_comp<C2, 2, 3, INV>(a);
+    } else if constexpr (R == 8) {
+        dft_comp<C2, 2, 4, INV>(a);
+    } else if constexpr (R == 12) {
+        dft_comp<C2, 4, 3, INV>(a);
+    } else if constexpr (R == 16) {
+        dft_comp<C2, 4, 4, INV>(a);
     } else {  // R == 5
+        static_assert(R == 5, "unsupported radix");
         const T c1 = (T)0.30901699437494742410229341718282;   // cos(2 pi/5)
         const T c2 = (T)-0.80901699437494742410229341718282;  // cos(4 pi/5)
         const T s1 = (T)0.95105651629515357211643933337938;   // sin(2 pi/5)
@@ -427,8 +560,12 @@ template <typename C2, int R, bool INV> __device__ inline void dft_small(C2 *a)
 // one, so the mask path is the common one (p is block-uniform).
 __device__ inline int mod_p(int i, int p) { return (p & (p - 1)) == 0 ? (i & (p - 1)) : i % p; }
 
+// Ring buffers in LDS hold element j at j + j/32: one pad slot per 32 keeps
+// the strided Stockham writes (stride R at p = 1) off shared banks.
+__device__ __forceinline__ int rix(int j) { return j + (j >> 5); }
+
 template <typename C2, int R, bool INV, int NMAX>
-__device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
+__device__ __forceinline__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw, int tid)
 {
     constexpr int MAXB = (NMAX / R + 255) / 256;
     const int nb = n / R;
@@ -438,7 +575,7 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
     const bool shared_k = (256 % p) == 0;
     C2 w0[R];
     if (shared_k) {
-        const int k = mod_p(threadIdx.x, p);
+        const int k = mod_p(tid, p);
 #pragma unroll
         for (int t = 1; t < R; t++) {
             w0[t] = tw[t * k * tstep];
@@ -448,11 +585,11 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
     C2 y[MAXB][R];
 #pragma unroll
     for (int c = 0; c < MAXB; c++) {
-        const int i = threadIdx.x + c * 256;
+        const int i = tid + c * 256;
         if (i < nb) {
             C2 xv[R];
 #pragma unroll
-            for (int t = 0; t < R; t++) xv[t] = buf[i + t * nb];
+            for (int t = 0; t < R; t++) xv[t] = buf[rix(i + t * nb)];
             if (shared_k) {
 #pragma unroll
                 for (int t = 1; t < R; t++) xv[t] = cmul(xv[t], w0[t]);
@@ -473,12 +610,12 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < MAXB; c++) {
-        const int i = threadIdx.x + c * 256;
+        const int i = tid + c * 256;
         if (i < nb) {
             const int k = mod_p(i, p);
             const int j = (i - k) * R + k;
 #pragma unroll
-            for (int t = 0; t < R; t++) buf[j + t * p] = y[c][t];
+            for (int t = 0; t < R; t++) buf[rix(j + t * p)] = y[c][t];
         }
     }
     __syncthreads();
@@ -487,7 +624,7 @@ __device__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw)
 // Compile-time pass of radix R with stride P over an N-point ring: the same
 // Stockham step as fft_pass with every index folded to constants.
 template <typename C2, int R, bool INV, int N, int P>
-__device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw)
+__device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw, int tid)
 {
     constexpr int NB = N / R;
     constexpr int TSTEP = N / (P * R);
@@ -495,7 +632,7 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw)
     constexpr bool SHARED_K = (256 % P) == 0;
     C2 w0[R];
     if constexpr (SHARED_K && P > 1) {
-        const int k = threadIdx.x % P;
+        const int k = tid % P;
 #pragma unroll
         for (int t = 1; t < R; t++) {
             w0[t] = tw[t * k * TSTEP];
@@ -505,11 +642,11 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw)
     C2 y[MAXB][R];
 #pragma unroll
     for (int c = 0; c < MAXB; c++) {
-        const int i = threadIdx.x + c * 256;
+        const int i = tid + c * 256;
         if (NB % 256 == 0 || i < NB) {
             C2 xv[R];
 #pragma unroll
-            for (int t = 0; t < R; t++) xv[t] = buf[i + t * NB];
+            for (int t = 0; t < R; t++) xv[t] = buf[rix(i + t * NB)];
             if constexpr (P > 1) {
                 if constexpr (SHARED_K) {
 #pragma unroll
@@ -532,22 +669,22 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw)
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < MAXB; c++) {
-        const int i = threadIdx.x + c * 256;
+        const int i = tid + c * 256;
         if (NB % 256 == 0 || i < NB) {
             const int k = i % P;
             const int j = (i - k) * R + k;
 #pragma unroll
-            for (int t = 0; t < R; t++) buf[j + t * P] = y[c][t];
+            for (int t = 0; t < R; t++) buf[rix(j + t * P)] = y[c][t];
         }
     }
     __syncthreads();
 }
 
 template <typename C2, bool INV, int N, int P, int R, int... Rest>
-__device__ __forceinline__ void fft_static(C2 *buf, const C2 *__restrict__ tw)
+__device__ __forceinline__ void fft_static(C2 *buf, const C2 *__restrict__ tw, int tid)
 {
-    fft_pass_c<C2, R, INV, N, P>(buf, tw);
-    if constexpr (sizeof...(Rest) > 0) fft_static<C2, INV, N, P * R, Rest...>(buf, tw);
+    fft_pass_c<C2, R, INV, N, P>(buf, tw, tid);
+    if constexpr (sizeof...(Rest) > 0) fft_static<C2, INV, N, P * R, Rest...>(buf, tw, tid);
 }
 
 // Ring lengths with a compile-time plan (the 3L grids of lmax 256..2048);
@@ -556,121 +693,155 @@ __device__ __forceinline__ void fft_static(C2 *buf, const C2 *__restrict__ tw)
 // rings run in the instantiation below it, and a plan longer than NMAX would
 // need more registers than the kernel reserves.
 template <typename C2, bool INV, int NMAX>
-__device__ __forceinline__ bool fft_planned(C2 *buf, int n, const C2 *__restrict__ tw)
+__device__ __forceinline__ bool fft_planned(C2 *buf, int n, const C2 *__restrict__ tw, int tid)
 {
     if constexpr (NMAX == 1024) {
-        if (n == 768) { fft_static<C2, INV, 768, 1, 4, 4, 4, 4, 3>(buf, tw); return true; }
-        if (n == 1024) { fft_static<C2, INV, 1024, 1, 4, 4, 4, 4, 4>(buf, tw); return true; }
+        if (n == 768) { fft_static<C2, INV, 768, 1, 16, 12, 4>(buf, tw, tid); return true; }
+        if (n == 1024) { fft_static<C2, INV, 1024, 1, 16, 16, 4>(buf, tw, tid); return true; }
     } else if constexpr (NMAX == 2048) {
-        if (n == 1536) { fft_static<C2, INV, 1536, 1, 4, 4, 4, 4, 2, 3>(buf, tw); return true; }
+        if (n == 1536) { fft_static<C2, INV, 1536, 1, 16, 16, 6>(buf, tw, tid); return true; }
     } else if constexpr (NMAX == 4096) {
-        if (n == 3072) { fft_static<C2, INV, 3072, 1, 4, 4, 4, 4, 4, 3>(buf, tw); return true; }
+        if (n == 3072) { fft_static<C2, INV, 3072, 1, 16, 16, 12>(buf, tw, tid); return true; }
     } else if constexpr (NMAX == 8192) {
-        if (n == 6144) { fft_static<C2, INV, 6144, 1, 4, 4, 4, 4, 4, 2, 3>(buf, tw); return true; }
+        if (n == 6144) { fft_static<C2, INV, 6144, 1, 16, 16, 12, 2>(buf, tw, tid); return true; }
     }
     return false;
 }
 
 // NMAX: longest ring this instantiation handles (registers are reserved for
 // NMAX / 256 elements per thread).
-template <typename C2, bool INV, int NMAX>
-__device__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw)
+// PLANNED: n has a compile-time plan (fft_has_plan); only that code is
+// compiled in, which keeps the register budget of the planned kernels to
+// what their passes need.
+template <typename C2, bool INV, int NMAX, bool PLANNED>
+__device__ __forceinline__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw, int tid)
 {
-    if (fft_planned<C2, INV, NMAX>(buf, sh.nphi, tw)) return;
+    if constexpr (PLANNED) {
+        (void)fft_planned<C2, INV, NMAX>(buf, sh.nphi, tw, tid);
+        return;
+    }
     int p = 1;
     for (int ps = 0; ps < sh.npass; ps++) {
         const int R = sh.radix[ps];
         if (R == 4)
-            fft_pass<C2, 4, INV, NMAX>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 4, INV, NMAX>(buf, sh.nphi, p, tw, tid);
         else if (R == 2)
-            fft_pass<C2, 2, INV, NMAX>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 2, INV, NMAX>(buf, sh.nphi, p, tw, tid);
         else if (R == 3)
-            fft_pass<C2, 3, INV, NMAX>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 3, INV, NMAX>(buf, sh.nphi, p, tw, tid);
         else
-            fft_pass<C2, 5, INV, NMAX>(buf, sh.nphi, p, tw);
+            fft_pass<C2, 5, INV, NMAX>(buf, sh.nphi, p, tw, tid);
         p *= R;
     }
 }
 
-// Block = (ring pair p, shell s).  The north and south rings travel together
-// as one complex sequence z = f_N + i f_S: spectrum Z_m = N_m + i S_m for
-// 0 <= m <= L and Z_{n-m} = conj(N_m) + i conj(S_m), with N = E + O and
-// S = E - O.  After the inverse FFT, w = f_N^2 + i f_S^2 goes through the
-// forward FFT and the two real spectra separate as (W_m + conj W_{n-m})/2 and
-// (W_m - conj W_{n-m})/(2i).  With n = 3L the DFT bin L also holds mode -2L
-// of the square, n conj(G_L)^2, which is subtracted.  Blocks are numbered so
-// that consecutive shells of one pair run on the same XCD (shared L2 lines).
-template <typename T, int NMAX>
+// Block = (ring pair p, S consecutive shells), 256 threads per shell.  The
+// north and south rings travel together as one complex sequence
+// z = f_N + i f_S: spectrum Z_m = N_m + i S_m for 0 <= m <= L and
+// Z_{n-m} = conj(N_m) + i conj(S_m), with N = E + O and S = E - O.  After the
+// inverse FFT, w = f_N^2 + i f_S^2 goes through the forward FFT and the two
+// real spectra separate as (W_m + conj W_{n-m})/2 and (W_m - conj W_{n-m})/(2i).
+// With n = 3L the DFT bin L also holds mode -2L of the square, n conj(G_L)^2,
+// which is subtracted.  G and F rows hold (E, O) interleaved per column, so
+// one (m, shell) is 4 contiguous values; the loads and stores map adjacent
+// threads to adjacent shells of the block (4 S contiguous values per m).
+// Blocks are numbered so that consecutive shell groups of one pair run on the
+// same XCD (shared L2 lines).
+template <typename T, int NMAX, int S, bool PLANNED>
 __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restrict__ wq,
                                           const typename Mt<T>::c2 *__restrict__ tw,
                                           const T *__restrict__ G, T *__restrict__ F,
                                           double *__restrict__ maps, int mode, int bid)
 {
     using C2 = typename Mt<T>::c2;
+    using Q = typename Mt<T>::quad;
     extern __shared__ unsigned char smem_raw[];
-    C2 *buf = reinterpret_cast<C2 *>(smem_raw);
-    const int L = sh.L, n = sh.nphi, Cpad = sh.Cpad;
-    const int nblk = sh.npair * sh.N;
+    const int L = sh.L, n = sh.nphi, Cpad = sh.Cpad, npad = ring_pad(n);
+    const int ngrp = (sh.N + S - 1) / S;
+    const int nblk = sh.npair * ngrp;
     const int nslot = (nblk + 7) / 8;
     const int logical = (bid & 7) * nslot + (bid >> 3);
-    if (logical >= nblk) return;
-    const int s = logical % sh.N, p = logical / sh.N;
-    const int tid = threadIdx.x;
+    if (logical >= nblk) return;  // whole block
+    const int s0 = (logical % ngrp) * S, p = logical / ngrp;
     const bool eq = sh.equator && p == sh.npair - 1;
+    // FFT role: shell s0 + g, thread tid of its 256
+    const int g = threadIdx.x >> 8, tid = threadIdx.x & 255;
+    C2 *buf = reinterpret_cast<C2 *>(smem_raw) + g * npad;
+    // load/store role: shell s0 + io, every S-th m from mq
+    const int io = threadIdx.x % S, mq = threadIdx.x / S;
+    C2 *iob = reinterpret_cast<C2 *>(smem_raw) + io * npad;
+    const bool iov = s0 + io < sh.N;
+    const T *Gp = G + ((long long)p * (L + 1) * Cpad + 2 * (s0 + io)) * 2;
 
     // bins (L, n - L) are empty; the loop below writes every other bin
     for (int q = L + 1 + tid; q < n - L; q += 256) {
         C2 z;
         z.x = T(0);
         z.y = T(0);
-        buf[q] = z;
+        buf[rix(q)] = z;
     }
-    const T *Gp = G + (long long)p * (L + 1) * 2 * Cpad + 2 * s;
-    for (int m = tid; m <= L; m += 256) {
-        const T *g = Gp + (long long)m * 2 * Cpad;
-        const T Er = g[0], Ei = g[1], Or = g[Cpad], Oi = g[Cpad + 1];
+    // every load of the thread is issued before the first is used (one
+    // memory latency per block instead of one per row)
+    constexpr int KM = (NMAX / 3 + 256) / 256;  // rows per thread: L <= n/3 <= NMAX/3
+    Q v[KM];
+#pragma unroll
+    for (int k = 0; k < KM; k++) {
+        const int m = mq + 256 * k;
+        if (iov && m <= L)
+            v[k] = *reinterpret_cast<const Q *>(Gp + (long long)m * Cpad * 2);
+        else
+            v[k] = Q{};
+    }
+#pragma unroll
+    for (int k = 0; k < KM; k++) {
+        const int m = mq + 256 * k;
+        if (m > L) break;
+        const T Er = v[k].x, Or = v[k].y, Ei = v[k].z, Oi = v[k].w;
         T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
         if (eq) Sr = Si = T(0);
         if (m == 0) Ni = Si = T(0);
         C2 z;
         z.x = Nr - Si;
         z.y = Ni + Sr;
-        buf[m] = z;
+        iob[rix(m)] = z;
         if (m > 0) {
             z.x = Nr + Si;
             z.y = Sr - Ni;
-            buf[n - m] = z;
+            iob[rix(n - m)] = z;
         }
     }
     __syncthreads();
-    fft_lds<C2, true, NMAX>(buf, sh, tw);
+    fft_lds<C2, true, NMAX, PLANNED>(buf, sh, tw, tid);
     if (mode == 1) {
-        const long long nr = sh.nring;
+        if (s0 + g >= sh.N) return;  // no barrier follows
+        const long long nr = sh.nring, sg = s0 + g;
         for (int j = tid; j < n; j += 256) {
-            maps[((long long)s * nr + p) * n + j] = (double)buf[j].x;
-            if (!eq) maps[((long long)s * nr + (nr - 1 - p)) * n + j] = (double)buf[j].y;
+            const C2 z = buf[rix(j)];
+            maps[(sg * nr + p) * n + j] = (double)z.x;
+            if (!eq) maps[(sg * nr + (nr - 1 - p)) * n + j] = (double)z.y;
         }
         return;
     }
     for (int j = tid; j < n; j += 256) {
-        C2 z = buf[j];
+        C2 z = buf[rix(j)];
         z.x = z.x * z.x;
         z.y = z.y * z.y;
-        buf[j] = z;
+        buf[rix(j)] = z;
     }
     __syncthreads();
-    fft_lds<C2, false, NMAX>(buf, sh, tw);
+    fft_lds<C2, false, NMAX, PLANNED>(buf, sh, tw, tid);
 
     const T wgt = (T)wq[p];
     const T half = T(0.5);
-    for (int m = tid; m <= L; m += 256) {
-        const C2 W1 = buf[m];
-        const C2 W2 = buf[m == 0 ? 0 : n - m];
+    T *Fp = F + ((long long)p * Cpad + 2 * (s0 + io)) * 2;
+    for (int m = mq; m <= L; m += 256) {
+        const C2 W1 = iob[rix(m)];
+        const C2 W2 = iob[rix(m == 0 ? 0 : n - m)];
         T Ar = half * (W1.x + W2.x), Ai = half * (W1.y - W2.y);
         T Br = half * (W1.y + W2.y), Bi = -half * (W1.x - W2.x);
-        if (sh.alias && m == L) {
-            const T *g = Gp + (long long)L * 2 * Cpad;
-            const T Er = g[0], Ei = g[1], Or = g[Cpad], Oi = g[Cpad + 1];
+        if (sh.alias && m == L && iov) {
+            const Q v = *reinterpret_cast<const Q *>(Gp + (long long)L * Cpad * 2);
+            const T Er = v.x, Or = v.y, Ei = v.z, Oi = v.w;
             T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
             if (eq) Sr = Si = T(0);
             const T fn = (T)n;
@@ -680,25 +851,27 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
             Bi -= fn * (-T(2) * Sr * Si);
         }
         if (eq) Br = Bi = T(0);
-        T FEr = wgt * (Ar + Br), FEi = wgt * (Ai + Bi);
-        T FOr = wgt * (Ar - Br), FOi = wgt * (Ai - Bi);
-        if (eq) FOr = FOi = T(0);
-        if (m == 0) FEi = FOi = T(0);
-        T *f = F + ((long long)m * sh.npair + p) * 2 * Cpad + 2 * s;
-        f[0] = FEr;
-        f[1] = FEi;
-        f[Cpad] = FOr;
-        f[Cpad + 1] = FOi;
+        Q f;
+        f.x = wgt * (Ar + Br);  // E re
+        f.y = wgt * (Ar - Br);  // O re
+        f.z = wgt * (Ai + Bi);  // E im
+        f.w = wgt * (Ai - Bi);  // O im
+        if (eq) f.y = f.w = T(0);
+        if (m == 0) f.z = f.w = T(0);
+        if (iov) *reinterpret_cast<Q *>(Fp + (long long)m * sh.npair * Cpad * 2) = f;
     }
 }
 
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void k_ring(Shape sh, const double *__restrict__ wq,
-                                              const typename Mt<T>::c2 *__restrict__ tw,
-                                              const T *__restrict__ G, T *__restrict__ F,
-                                              double *__restrict__ maps, int mode)
+// shells per ring block: 2 in FP32 (512 threads), 1 in FP64
+template <typename T> constexpr int ring_s() { return sizeof(T) == 4 ? kRingShellsF32 : kRingShellsF64; }
+
+template <typename T, int NMAX, bool PLANNED>
+__global__ __launch_bounds__(256 * ring_s<T>()) void k_ring(Shape sh, const double *__restrict__ wq,
+                                                            const typename Mt<T>::c2 *__restrict__ tw,
+                                                            const T *__restrict__ G, T *__restrict__ F,
+                                                            double *__restrict__ maps, int mode)
 {
-    body_ring<T, NMAX>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
+    body_ring<T, NMAX, ring_s<T>(), PLANNED>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
 }
 
 // --------------------------------------------------------- Legendre analysis
@@ -777,14 +950,16 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
         // B operands F_{E/O}[pair][column] of a K-step (4 pairs), loaded one step
         // ahead; pairs past the last one read the next m (or the zero padding
         // after the last m) and meet lambda = 0 exactly
-        const T *fbase = F + ((long long)m * npair + pc * kAnalPC + k4) * 2 * Cpad + colb;
+        // F[m][pair][column] holds (E, O) interleaved
+        const T *fbase = F + (((long long)m * npair + pc * kAnalPC + k4) * Cpad + colb) * 2;
         T fE[CF], fO[CF], gE_[CF], gO_[CF];
         auto loadF = [&](int kk, T *E, T *O) {
-            const T *f = fbase + (long long)(4 * kk) * 2 * Cpad;
+            const T *f = fbase + (long long)(4 * kk) * Cpad * 2;
 #pragma unroll
             for (int cf = 0; cf < CF; cf++) {
-                E[cf] = f[16 * cf];
-                O[cf] = f[Cpad + 16 * cf];
+                const typename M::c2v v = *reinterpret_cast<const typename M::c2v *>(f + 32 * cf);
+                E[cf] = v.x;
+                O[cf] = v.y;
             }
         };
         loadF(0, fE, fO);
@@ -1028,16 +1203,16 @@ __global__ __launch_bounds__(64, synth_waves<T>()) void g_synth(const GroupItem 
                       (const T *)g.b.phi, (T *)g.b.G, lb);
 }
 
-template <typename T, int NMAX>
-__global__ __launch_bounds__(256) void g_ring(const GroupItem *__restrict__ it,
+template <typename T, int NMAX, bool PLANNED>
+__global__ __launch_bounds__(256 * ring_s<T>()) void g_ring(const GroupItem *__restrict__ it,
                                               const int *__restrict__ ord,
                                               const int *__restrict__ off, int n)
 {
     int lb;
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
-    body_ring<T, NMAX>(g.sh, g.b.wq, (const typename Mt<T>::c2 *)g.b.tw, (const T *)g.b.G, (T *)g.b.F,
-                 nullptr, 0, lb);
+    body_ring<T, NMAX, ring_s<T>(), PLANNED>(g.sh, g.b.wq, (const typename Mt<T>::c2 *)g.b.tw,
+                                    (const T *)g.b.G, (T *)g.b.F, nullptr, 0, lb);
 }
 
 template <typename T, int CF>
@@ -1180,7 +1355,7 @@ __global__ __launch_bounds__(256) void k_radial_adj(Shape sh, const double *__re
 // transposed synthesis needs c_m sum_pix phibar e^{-i m phi}; with n = 3L the
 // bin L also holds mode -2L of phibar, 2 f_NL w conj(G_L) conj(G2_L) n, which
 // is removed.
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool PLANNED>
 __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__restrict__ wq,
                                                   const typename Mt<T>::c2 *__restrict__ tw,
                                                   const T *__restrict__ G,
@@ -1188,10 +1363,11 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
                                                   double *__restrict__ fpart, double fnl)
 {
     using C2 = typename Mt<T>::c2;
+    using Q = typename Mt<T>::quad;
     extern __shared__ unsigned char smem_raw[];
     const int L = sh.L, n = sh.nphi, Cpad = sh.Cpad;
     C2 *b1 = reinterpret_cast<C2 *>(smem_raw);
-    C2 *b2 = b1 + n;
+    C2 *b2 = b1 + ring_pad(n);
     __shared__ double red[256];
     const int nblk = sh.npair * sh.N;
     const int nslot = (nblk + 7) / 8;
@@ -1205,16 +1381,17 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         C2 z;
         z.x = T(0);
         z.y = T(0);
-        b1[q] = z;
-        b2[q] = z;
+        b1[rix(q)] = z;
+        b2[rix(q)] = z;
     }
     __syncthreads();
-    const long long poff = (long long)p * (L + 1) * 2 * Cpad + 2 * s;
+    // G, G2 and F rows hold (E, O) interleaved per column
+    const long long poff = ((long long)p * (L + 1) * Cpad + 2 * s) * 2;
     for (int m = tid; m <= L; m += 256) {
 #pragma unroll
         for (int which = 0; which < 2; which++) {
-            const T *g = (which ? G2 : G) + poff + (long long)m * 2 * Cpad;
-            const T Er = g[0], Ei = g[1], Or = g[Cpad], Oi = g[Cpad + 1];
+            const Q v = *reinterpret_cast<const Q *>((which ? G2 : G) + poff + (long long)m * Cpad * 2);
+            const T Er = v.x, Or = v.y, Ei = v.z, Oi = v.w;
             T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
             if (eq) Sr = Si = T(0);
             if (m == 0) Ni = Si = T(0);
@@ -1222,23 +1399,23 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
             C2 z;
             z.x = Nr - Si;
             z.y = Ni + Sr;
-            bb[m] = z;
+            bb[rix(m)] = z;
             if (m > 0) {
                 z.x = Nr + Si;
                 z.y = Sr - Ni;
-                bb[n - m] = z;
+                bb[rix(n - m)] = z;
             }
         }
     }
     __syncthreads();
-    fft_lds<C2, true, NMAX>(b1, sh, tw);
-    fft_lds<C2, true, NMAX>(b2, sh, tw);
+    fft_lds<C2, true, NMAX, PLANNED>(b1, sh, tw, tid);
+    fft_lds<C2, true, NMAX, PLANNED>(b2, sh, tw, tid);
     const T wpix = (T)wq[p];
     const T two_f = (T)(2.0 * fnl);
     double fb = 0.0;
     for (int j = tid; j < n; j += 256) {
-        const C2 f = b1[j];
-        C2 g = b2[j];
+        const C2 f = b1[rix(j)];
+        C2 g = b2[rix(j)];
         g.x *= wpix;
         g.y *= wpix;
         fb += (double)f.x * (double)f.x * (double)g.x;
@@ -1246,21 +1423,21 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         C2 ph;
         ph.x = two_f * f.x * g.x;
         ph.y = eq ? T(0) : two_f * f.y * g.y;
-        b1[j] = ph;
+        b1[rix(j)] = ph;
     }
     // Phi_L^2 ghat has modes up to 3L along the ring; with n = 3L the pixel sum
     // also picks up modes +-3L, 2 Re(G_L^2 G2_L) per ring (times n and the
     // pixel weight), which are removed.
     if (sh.alias && tid == 0) {
-        const T *g = G + poff + (long long)L * 2 * Cpad;
-        const T *h = G2 + poff + (long long)L * 2 * Cpad;
-        const double Nr = (double)g[0] + (double)g[Cpad], Ni = (double)g[1] + (double)g[Cpad + 1];
-        const double Mr = (double)h[0] + (double)h[Cpad], Mi = (double)h[1] + (double)h[Cpad + 1];
+        const Q g = *reinterpret_cast<const Q *>(G + poff + (long long)L * Cpad * 2);
+        const Q h = *reinterpret_cast<const Q *>(G2 + poff + (long long)L * Cpad * 2);
+        const double Nr = (double)g.x + (double)g.y, Ni = (double)g.z + (double)g.w;
+        const double Mr = (double)h.x + (double)h.y, Mi = (double)h.z + (double)h.w;
         // Re(N^2 M) = (Nr^2 - Ni^2) Mr - 2 Nr Ni Mi
         double a = (Nr * Nr - Ni * Ni) * Mr - 2.0 * Nr * Ni * Mi;
         if (!eq) {
-            const double Sr = (double)g[0] - (double)g[Cpad], Si = (double)g[1] - (double)g[Cpad + 1];
-            const double Rr = (double)h[0] - (double)h[Cpad], Ri = (double)h[1] - (double)h[Cpad + 1];
+            const double Sr = (double)g.x - (double)g.y, Si = (double)g.z - (double)g.w;
+            const double Rr = (double)h.x - (double)h.y, Ri = (double)h.z - (double)h.w;
             a += (Sr * Sr - Si * Si) * Rr - 2.0 * Sr * Si * Ri;
         }
         fb -= 2.0 * (double)n * (double)wpix * a;
@@ -1272,20 +1449,20 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         __syncthreads();
     }
     if (tid == 0) fpart[(long long)p * sh.N + s] = red[0];
-    fft_lds<C2, false, NMAX>(b1, sh, tw);
+    fft_lds<C2, false, NMAX, PLANNED>(b1, sh, tw, tid);
     const T half = T(0.5);
     for (int m = tid; m <= L; m += 256) {
-        const C2 W1 = b1[m];
-        const C2 W2 = b1[m == 0 ? 0 : n - m];
+        const C2 W1 = b1[rix(m)];
+        const C2 W2 = b1[rix(m == 0 ? 0 : n - m)];
         T Ar = half * (W1.x + W2.x), Ai = half * (W1.y - W2.y);
         T Br = half * (W1.y + W2.y), Bi = -half * (W1.x - W2.x);
         if (sh.alias && m == L) {
-            const T *g = G + poff + (long long)L * 2 * Cpad;
-            const T *h = G2 + poff + (long long)L * 2 * Cpad;
-            T Nr = g[0] + g[Cpad], Ni = g[1] + g[Cpad + 1];
-            T Sr = g[0] - g[Cpad], Si = g[1] - g[Cpad + 1];
-            T Mr = h[0] + h[Cpad], Mi = h[1] + h[Cpad + 1];
-            T Rr = h[0] - h[Cpad], Ri = h[1] - h[Cpad + 1];
+            const Q g = *reinterpret_cast<const Q *>(G + poff + (long long)L * Cpad * 2);
+            const Q h = *reinterpret_cast<const Q *>(G2 + poff + (long long)L * Cpad * 2);
+            T Nr = g.x + g.y, Ni = g.z + g.w;
+            T Sr = g.x - g.y, Si = g.z - g.w;
+            T Mr = h.x + h.y, Mi = h.z + h.w;
+            T Rr = h.x - h.y, Ri = h.z - h.w;
             if (eq) Sr = Si = Rr = Ri = T(0);
             const T k = (T)n * two_f * wpix;
             // conj(N) conj(M) = (Nr Mr - Ni Mi, -(Nr Mi + Ni Mr))
@@ -1300,11 +1477,12 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         T FOr = cm * (Ar - Br), FOi = cm * (Ai - Bi);
         if (eq) FOr = FOi = T(0);
         if (m == 0) FEi = FOi = T(0);
-        T *f = F + ((long long)m * sh.npair + p) * 2 * Cpad + 2 * s;
-        f[0] = FEr;
-        f[1] = FEi;
-        f[Cpad] = FOr;
-        f[Cpad + 1] = FOi;
+        Q q;
+        q.x = FEr;
+        q.y = FOr;
+        q.z = FEi;
+        q.w = FOi;
+        *reinterpret_cast<Q *>(F + (((long long)m * sh.npair + p) * Cpad + 2 * s) * 2) = q;
     }
 }
 
@@ -1470,22 +1648,31 @@ hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void
 }
 
 // Smallest supported maximum ring length covering n.
-static int nmax_for(int n) { return n <= 1024 ? 1024 : n <= 2048 ? 2048 : n <= 4096 ? 4096 : 8192; }
+static int nmax_for(int n) { return ring_bucket(n); }
 
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool PLANNED>
 static hipError_t ring_t(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
                          double *maps, int mode, hipStream_t s)
 {
     using C2 = typename Mt<T>::c2;
-    const long long nblk = (long long)sh.npair * sh.N;
+    constexpr int S = ring_s<T>();
+    const long long nblk = (long long)sh.npair * ((sh.N + S - 1) / S);
     dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
-    const size_t lds = sizeof(C2) * sh.nphi;
+    const size_t lds = S * sizeof(C2) * ring_pad(sh.nphi);
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_ring<T, NMAX>,
+        (void)hipFuncSetAttribute((const void *)k_ring<T, NMAX, PLANNED>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_ring<T, NMAX>), grid, dim3(256), lds, s, sh, b.wq, (const C2 *)b.tw,
-                       (const T *)G_in, (T *)F_out, maps, mode);
+    hipLaunchKernelGGL((k_ring<T, NMAX, PLANNED>), grid, dim3(256 * S), lds, s, sh, b.wq,
+                       (const C2 *)b.tw, (const T *)G_in, (T *)F_out, maps, mode);
     return hipGetLastError();
+}
+
+template <typename T, int NMAX>
+static hipError_t ring_p(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                         double *maps, int mode, hipStream_t s)
+{
+    return fft_has_plan(sh.nphi) ? ring_t<T, NMAX, true>(sh, b, G_in, F_out, maps, mode, s)
+                                 : ring_t<T, NMAX, false>(sh, b, G_in, F_out, maps, mode, s);
 }
 
 template <typename T>
@@ -1493,11 +1680,12 @@ static hipError_t ring_n(const Shape &sh, const Bufs &b, const void *G_in, void 
                          double *maps, int mode, hipStream_t s)
 {
     switch (nmax_for(sh.nphi)) {
-    case 1024: return ring_t<T, 1024>(sh, b, G_in, F_out, maps, mode, s);
-    case 2048: return ring_t<T, 2048>(sh, b, G_in, F_out, maps, mode, s);
-    case 4096: return ring_t<T, 4096>(sh, b, G_in, F_out, maps, mode, s);
-    default: return ring_t<T, 8192>(sh, b, G_in, F_out, maps, mode, s);
+    case 1024: return ring_p<T, 1024>(sh, b, G_in, F_out, maps, mode, s);
+    case 2048: return ring_p<T, 2048>(sh, b, G_in, F_out, maps, mode, s);
+    case 4096: return ring_p<T, 4096>(sh, b, G_in, F_out, maps, mode, s);
+    default: return ring_p<T, 8192>(sh, b, G_in, F_out, maps, mode, s);
     }
+    return hipGetLastError();
 }
 
 hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
@@ -1590,20 +1778,28 @@ hipError_t launch_radial_adj(const Shape &sh, const Bufs &b, const double2 *gT, 
     return hipGetLastError();
 }
 
-template <typename T, int NMAX>
+template <typename T, int NMAX, bool PLANNED>
 static hipError_t ring_adj_t(const Shape &sh, const Bufs &b, const void *G, const void *G2,
                              void *F, double *fpart, double fnl, hipStream_t s)
 {
     using C2 = typename Mt<T>::c2;
     const long long nblk = (long long)sh.npair * sh.N;
     dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
-    const size_t lds = 2 * sizeof(C2) * sh.nphi;
+    const size_t lds = 2 * sizeof(C2) * ring_pad(sh.nphi);
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_ring_adj<T, NMAX>,
+        (void)hipFuncSetAttribute((const void *)k_ring_adj<T, NMAX, PLANNED>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_ring_adj<T, NMAX>), grid, dim3(256), lds, s, sh, b.wq, (const C2 *)b.tw,
-                       (const T *)G, (const T *)G2, (T *)F, fpart, fnl);
+    hipLaunchKernelGGL((k_ring_adj<T, NMAX, PLANNED>), grid, dim3(256), lds, s, sh, b.wq,
+                       (const C2 *)b.tw, (const T *)G, (const T *)G2, (T *)F, fpart, fnl);
     return hipGetLastError();
+}
+
+template <typename T, int NMAX>
+static hipError_t ring_adj_p(const Shape &sh, const Bufs &b, const void *G, const void *G2,
+                             void *F, double *fpart, double fnl, hipStream_t s)
+{
+    return fft_has_plan(sh.nphi) ? ring_adj_t<T, NMAX, true>(sh, b, G, G2, F, fpart, fnl, s)
+                                 : ring_adj_t<T, NMAX, false>(sh, b, G, G2, F, fpart, fnl, s);
 }
 
 template <typename T>
@@ -1611,10 +1807,10 @@ static hipError_t ring_adj_n(const Shape &sh, const Bufs &b, const void *G, cons
                              void *F, double *fpart, double fnl, hipStream_t s)
 {
     switch (nmax_for(sh.nphi)) {
-    case 1024: return ring_adj_t<T, 1024>(sh, b, G, G2, F, fpart, fnl, s);
-    case 2048: return ring_adj_t<T, 2048>(sh, b, G, G2, F, fpart, fnl, s);
-    case 4096: return ring_adj_t<T, 4096>(sh, b, G, G2, F, fpart, fnl, s);
-    default: return ring_adj_t<T, 8192>(sh, b, G, G2, F, fpart, fnl, s);
+    case 1024: return ring_adj_p<T, 1024>(sh, b, G, G2, F, fpart, fnl, s);
+    case 2048: return ring_adj_p<T, 2048>(sh, b, G, G2, F, fpart, fnl, s);
+    case 4096: return ring_adj_p<T, 4096>(sh, b, G, G2, F, fpart, fnl, s);
+    default: return ring_adj_p<T, 8192>(sh, b, G, G2, F, fpart, fnl, s);
     }
 }
 
@@ -1654,7 +1850,10 @@ long long group_blocks(int stage, const Shape &sh, const Bufs &b)
     case GS_COMBINE: return (sh.nlm + 255) / 256;
     case GS_FILTER: return (long long)b.nk1 * (b.Mpad / 64);
     case GS_SYNTH: return b.nk2;
-    case GS_RING: return ((long long)sh.npair * sh.N + 7) / 8 * 8;
+    case GS_RING: {
+        const int S = ring_shells(sh.fp32);
+        return ((long long)sh.npair * ((sh.N + S - 1) / S) + 7) / 8 * 8;
+    }
     case GS_ANAL: return b.nk4;
     default: return 0;
     }
@@ -1670,6 +1869,20 @@ static void group_cf(int stage, const GroupItem *it, const int *ord, const int *
         hipLaunchKernelGGL((g_anal<T, CF>), grid, dim3(64), 0, s, it, ord, off, n);
 }
 
+template <typename T, bool PLANNED>
+static void ring_group_launch(int nmax, dim3 grid, dim3 blk, size_t lds, hipStream_t s,
+                              const GroupItem *it, const int *ord, const int *off, int n)
+{
+    if (nmax == 1024)
+        hipLaunchKernelGGL((g_ring<T, 1024, PLANNED>), grid, blk, lds, s, it, ord, off, n);
+    else if (nmax == 2048)
+        hipLaunchKernelGGL((g_ring<T, 2048, PLANNED>), grid, blk, lds, s, it, ord, off, n);
+    else if (nmax == 4096)
+        hipLaunchKernelGGL((g_ring<T, 4096, PLANNED>), grid, blk, lds, s, it, ord, off, n);
+    else
+        hipLaunchKernelGGL((g_ring<T, 8192, PLANNED>), grid, blk, lds, s, it, ord, off, n);
+}
+
 template <typename T>
 static void group_t(int stage, int CF, const GroupItem *it, const int *ord, const int *off, int n,
                     dim3 grid, size_t lds, hipStream_t s)
@@ -1680,15 +1893,16 @@ static void group_t(int stage, int CF, const GroupItem *it, const int *ord, cons
         break;
     case GS_FILTER: hipLaunchKernelGGL(g_filter<T>, grid, dim3(256), 0, s, it, ord, off, n); break;
     case GS_RING: {
-        const int nmax = nmax_for((int)(lds / sizeof(typename Mt<T>::c2)));
-        if (nmax == 1024)
-            hipLaunchKernelGGL((g_ring<T, 1024>), grid, dim3(256), lds, s, it, ord, off, n);
-        else if (nmax == 2048)
-            hipLaunchKernelGGL((g_ring<T, 2048>), grid, dim3(256), lds, s, it, ord, off, n);
-        else if (nmax == 4096)
-            hipLaunchKernelGGL((g_ring<T, 4096>), grid, dim3(256), lds, s, it, ord, off, n);
+        // `lds` is the longest ring of the group here; CF != 0 marks a group
+        // whose ring lengths all have compile-time plans
+        const int nmax = nmax_for((int)lds);
+        constexpr int S = ring_s<T>();
+        lds = S * sizeof(typename Mt<T>::c2) * ring_pad((int)lds);
+        const dim3 blk(256 * S);
+        if (CF)
+            ring_group_launch<T, true>(nmax, grid, blk, lds, s, it, ord, off, n);
         else
-            hipLaunchKernelGGL((g_ring<T, 8192>), grid, dim3(256), lds, s, it, ord, off, n);
+            ring_group_launch<T, false>(nmax, grid, blk, lds, s, it, ord, off, n);
         break;
     }
     case GS_COMBINE: hipLaunchKernelGGL(g_combine, grid, dim3(256), 0, s, it, ord, off, n); break;
@@ -1715,21 +1929,23 @@ hipError_t launch_group(int stage, int fp32, int CF, const GroupItem *items, con
     return hipGetLastError();
 }
 
-template <typename T>
-static hipError_t prep_ring_t(size_t lds)
+template <typename T, bool PLANNED>
+static hipError_t prep_ring_t(int nphi)
 {
-    const int nmax = nmax_for((int)(lds / sizeof(typename Mt<T>::c2)));
-    const void *f = nmax == 1024   ? (const void *)g_ring<T, 1024>
-                    : nmax == 2048 ? (const void *)g_ring<T, 2048>
-                    : nmax == 4096 ? (const void *)g_ring<T, 4096>
-                                   : (const void *)g_ring<T, 8192>;
+    const int nmax = nmax_for(nphi);
+    const size_t lds = ring_s<T>() * sizeof(typename Mt<T>::c2) * ring_pad(nphi);
+    if (lds <= 65536) return hipSuccess;
+    const void *f = nmax == 1024   ? (const void *)g_ring<T, 1024, PLANNED>
+                    : nmax == 2048 ? (const void *)g_ring<T, 2048, PLANNED>
+                    : nmax == 4096 ? (const void *)g_ring<T, 4096, PLANNED>
+                                   : (const void *)g_ring<T, 8192, PLANNED>;
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t prepare_group_ring(int fp32, size_t lds)
+hipError_t prepare_group_ring(int fp32, int nphi, int planned)
 {
-    if (lds <= 65536) return hipSuccess;
-    return fp32 ? prep_ring_t<float>(lds) : prep_ring_t<double>(lds);
+    if (fp32) return planned ? prep_ring_t<float, true>(nphi) : prep_ring_t<float, false>(nphi);
+    return planned ? prep_ring_t<double, true>(nphi) : prep_ring_t<double, false>(nphi);
 }
 
 }  // namespace fnl
