@@ -13,6 +13,7 @@ paper_0909_0009_amd/inputs.py) and resident in HBM before timing starts.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -52,6 +53,32 @@ def stage_work(sim, stage, precision):
     return "hbm", 0.0, "byte"
 
 
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_0909_0009_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(stage, precision):
+    """HBM bytes per launch of a stage's kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record (profiles/hbm_traffic.json), or None when
+    the kernel sources have changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != kernel_source_hash():
+        return None
+    T = "float" if precision == "fp32" else "double"
+    pat = re.compile(rf"^k_{stage}<{T}[,>]")
+    hits = [v for k, v in rec["kernels"].items() if pat.match(k)]
+    return round(hits[0]["traffic_bytes"]) if len(hits) == 1 else None
+
+
 def roofline(sim, stages, precision, steps):
     """Roofline object for the stage with the largest total time."""
     dom = max(stages, key=lambda k: stages[k][0])
@@ -67,7 +94,8 @@ def roofline(sim, stages, precision, steps):
         peak = PEAK["hbm_GBs"]
         u = "GB/s"
     return dom, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": u,
-                 "frac": round(achieved / peak, 4), "traffic": None,
+                 "frac": round(achieved / peak, 4), "traffic": measured_traffic(dom, precision),
+                 "traffic_unit": "byte",
                  "kernel": dom, "avg_launch_ms": round(avg_s * 1e3, 4),
                  "work_per_launch": work, "work_unit": unit}
 
