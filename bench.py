@@ -130,6 +130,99 @@ def time_path(torch, fnlsim, p, cfg, noise_np, precision, steps, warmup):
     return res
 
 
+def time_fwd_bwd(torch, fnlsim, inputs, precision, steps, warmup):
+    """Forward + hand-written reverse pass per step at the differentiation
+    workload (lmax 512, 96 nodes, 769 x 1536 grid), one realization."""
+    import numpy as np
+    cfg = inputs.CONFIGS["grad"]
+    L, N = cfg["lmax"], cfg["nshell"]
+    p = inputs.problem(L, N)
+    sim = fnlsim.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                           n_ring=cfg["ntheta"], n_phi=cfg["nphi"], precision=precision)
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    noise = torch.from_numpy(inputs.noise(L, N, inputs.realization_seed(0))).to(dt).cuda()
+    rng = np.random.default_rng(3)
+    gT = torch.from_numpy(rng.standard_normal((1, sim.n_lm)) + 1j * rng.standard_normal((1, sim.n_lm))).cuda()
+    gE = torch.zeros_like(gT)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sim.forward(noise, cfg["fnl"])
+        sim.backward(noise, cfg["fnl"], gT, gE)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        step()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sim.close()
+    return {"value": round(1000.0 / ms, 3), "unit": "fwd+bwd maps/s", "ms_per_step": round(ms, 4),
+            "workload": f"lmax={L}, {N} radial nodes, {cfg['ntheta']}x{cfg['nphi']} grid, "
+                        f"gradients w.r.t. the noise and f_NL"}
+
+
+def time_batch(torch, fnlsim, inputs, precision, steps, warmup):
+    """Uneven batching workload: 32 realizations with lmax in {128, 256, 512,
+    1024} and 64..200 nodes, one grouped graph-captured launch per stage,
+    against the same 32 forward passes issued one after another."""
+    mix = inputs.batch_mix()
+    dt = torch.complex128 if precision == "fp64" else torch.complex64
+    sims, noises, fnls = [], [], []
+    t0 = time.time()
+    probs = {}
+    for i, (L, N) in enumerate(mix):
+        if (L, N) not in probs:
+            probs[(L, N)] = inputs.problem(L, N)
+            log(f"batch input {i + 1}/{len(mix)}: lmax {L}, {N} nodes ({time.time() - t0:.0f} s)")
+    log(f"batch inputs ready in {time.time() - t0:.1f} s")
+    for i, (L, N) in enumerate(mix):
+        p = probs[(L, N)]
+        sims.append(fnlsim.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                                     precision=precision))
+        noises.append(torch.from_numpy(inputs.noise(L, N, inputs.realization_seed(i))).to(dt).cuda())
+        fnls.append(50.0)
+    batch = fnlsim.Batch(sims)
+    outs = batch.forward(noises, fnls)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_b = timed(lambda: batch.forward(noises, fnls, outs))
+    ms_s = timed(lambda: [s.forward(x, f) for s, x, f in zip(sims, noises, fnls)])
+    # the batched result equals the per-context one
+    worst = 0.0
+    for s, x, f, o in zip(sims, noises, fnls, outs):
+        aT, aE = s.forward(x, f)
+        worst = max(worst, float((aT - o[0]).abs().max() / aT.abs().max()),
+                    float((aE - o[1]).abs().max() / aE.abs().max()))
+    batch.close()
+    for s in sims:
+        s.close()
+    return {"realizations": len(mix), "batched_ms": round(ms_b, 3), "sequential_ms": round(ms_s, 3),
+            "batched_maps_per_s": round(1000.0 * len(mix) / ms_b, 2),
+            "sequential_maps_per_s": round(1000.0 * len(mix) / ms_s, 2),
+            "speedup": round(ms_s / ms_b, 3), "max_rel_diff_vs_sequential": worst,
+            "workload": "32 realizations, lmax in {128,256,512,1024}, 64..200 nodes "
+                        "(default_rng(33)), n_theta = ceil((3L+1)/2), n_phi = 3L, f_NL = 50"}
+
+
 def per_l_rel_err(a, ref, L):
     import numpy as np
     ls = np.repeat(np.arange(L + 1), np.arange(1, L + 2))
@@ -176,6 +269,9 @@ def main():
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
+    ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd leg (lmax 512)")
+    ap.add_argument("--batch", action="store_true",
+                    help="also time the uneven 32-realization batch against sequential calls")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -229,6 +325,19 @@ def main():
         r64["sim"].close()
         torch.cuda.empty_cache()
 
+    grad = None
+    if not args.no_grad:
+        grad = {"fp32": time_fwd_bwd(torch, fnlsim, inputs, "fp32", args.steps, args.warmup)}
+        if not args.fp32_only:
+            grad["fp64"] = time_fwd_bwd(torch, fnlsim, inputs, "fp64", args.steps, args.warmup)
+        log(f"fwd+bwd: {grad}")
+        torch.cuda.empty_cache()
+    batch = None
+    if args.batch:
+        batch = {"fp32": time_batch(torch, fnlsim, inputs, "fp32", args.steps, args.warmup)}
+        log(f"batch: {batch}")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(p, cfg, noise_np, args.cpu_shells)
@@ -257,6 +366,8 @@ def main():
         "roofline": roof,
         "fp64": fp64,
         "mixed_vs_fp64_max_rel_err": err,
+        "fwd_bwd": grad,
+        "batch": batch,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

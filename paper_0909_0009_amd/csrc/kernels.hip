@@ -48,6 +48,37 @@ template <> struct Mt<float> {
     __device__ static constexpr int row(int k4, int r) { return 4 * k4 + r; }
 };
 
+// Global-memory pointers: indexing through them emits global (not flat)
+// memory instructions, and scalar loads where the address is uniform, also
+// where the pointer value was read from memory (the grouped launches take
+// every context's buffers from an item table).
+#define GLB __attribute__((address_space(1)))
+template <typename P> __device__ __forceinline__ GLB P *glb(P *p) { return (GLB P *)p; }
+
+// HIP's vector types are classes that cannot be copied out of (or into) a
+// global-qualified lvalue; these move them as one builtin vector access.
+template <typename V> struct VecOf;
+template <> struct VecOf<int2> { typedef int t __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<int4> { typedef int t __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<float2> { typedef float t __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float4> { typedef float t __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<double2> { typedef double t __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<double4> { typedef double t __attribute__((ext_vector_type(4))); };
+template <typename V> __device__ __forceinline__ V gload(const GLB V *p)
+{
+    static_assert(sizeof(V) == sizeof(typename VecOf<V>::t), "vector size");
+    const typename VecOf<V>::t v = *reinterpret_cast<const GLB typename VecOf<V>::t *>(p);
+    V out;
+    __builtin_memcpy(&out, &v, sizeof(V));
+    return out;
+}
+template <typename V> __device__ __forceinline__ void gstore(GLB V *p, const V &val)
+{
+    typename VecOf<V>::t v;
+    __builtin_memcpy(&v, &val, sizeof(V));
+    *reinterpret_cast<GLB typename VecOf<V>::t *>(p) = v;
+}
+
 __device__ inline int l_of_index(long long idx) {
     int l = (int)((sqrt(8.0 * (double)idx + 1.0) - 1.0) * 0.5);
     while ((long long)l * (l + 1) / 2 > idx) --l;
@@ -57,72 +88,158 @@ __device__ inline int l_of_index(long long idx) {
 
 // ---------------------------------------------------------------- filter
 
-// Block = (l, 64-column tile) x 64-row tile.  4 waves in a 2x2 layout, each
-// owning 32x32 outputs (2x2 MFMA tiles).  Columns are c = 2m + (re/im) of
-// the noise row n[j][idx(l, 0) ..], so a complex coefficient is two real
-// columns and the real filter multiplies both.
+// Block = (l, 64-column tile), every output row.  Columns are c = 2m +
+// (re/im) of the noise row n[j][idx(l, 0) ..], so a complex coefficient is
+// two real columns and the real filter multiplies both.  Rows come in
+// RT = ceil(N/32) tiles of 32; wave w owns the tile pairs (t, RT-1-t) with
+// t = w, w+4, .. (one pair per wave for N <= 256), so with a lower-triangular
+// F (tile t only needs j < 32 t + 32) the four waves do equal work.  The noise
+// rows of a 32-row K-chunk are staged in LDS, double buffered, and shared by
+// the four waves; the F^T fragments of the next chunk load while the block
+// waits at the chunk's barrier.  The noise is read from HBM once.
+constexpr int kFiltLD = 80;  // LDS row stride (elements): conflict-free B reads
+// blocks per CU the filter's register budget is held to (FP64 holds twice
+// the accumulator registers)
+template <typename T> constexpr int filter_blocks() { return sizeof(T) == 4 ? 2 : 1; }
+
 template <typename T>
-__device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FT, int Kpad,
-                                            int Mpad, const int2 *__restrict__ tiles,
-                                            const T *__restrict__ noise, T *__restrict__ phi,
-                                            int bx, int by)
+__device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FT_in, int Kpad,
+                                            int Mpad, const int2 *__restrict__ tiles_in,
+                                            const T *__restrict__ noise_in, T *__restrict__ phi_in,
+                                            int bx)
 {
+    auto *__restrict__ FT = glb(FT_in);
+    auto *__restrict__ tiles = glb(tiles_in);
+    auto *__restrict__ noise = glb(noise_in);
+    auto *__restrict__ phi = glb(phi_in);
     using M = Mt<T>;
-    const int2 tl = tiles[bx];
-    const int l = tl.x, ct = tl.y;
-    const int row0 = by * 64;
+    using C2 = typename M::c2;
+    __shared__ T nz[2][32][kFiltLD];
+    const int2 tl = gload(tiles + bx);
+    const int l = tl.x, col0 = tl.y * 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int wr = wave >> 1, wc = wave & 1;
     const int i16 = lane & 15, k4 = lane >> 4;
-    const int ncol = 2 * (l + 1);
+    const int N = sh.N, ncol = 2 * (l + 1);
     const long long nlm = sh.nlm;
     const long long base = 2 * lm_index(l, 0);
-    const T *FTl = FT + (long long)l * Kpad * Mpad;
-    typename M::acc acc[2][2];
-    for (int a = 0; a < 2; a++)
-        for (int c = 0; c < 2; c++) acc[a][c] = typename M::acc{};
-    const int rowA = row0 + 32 * wr + i16;
-    const int colB = ct * 64 + 32 * wc + i16;
-    // lower-triangular F: rows < row0 + 64 need columns j < row0 + 64 only
-    const int jend = sh.lower ? min(Kpad, row0 + 64) : Kpad;
-    for (int j0 = 0; j0 < jend; j0 += 4) {
-        const int j = j0 + k4;
-        T av[2], bv[2];
+    const auto FTl = FT + (long long)l * Kpad * Mpad;
+    const int RT = (N + 31) / 32, npairs = (RT + 1) / 2;
+    // staging role: thread t loads chunk row t / 8, columns 8 (t % 8) .. + 8
+    const int sj = threadIdx.x >> 3, sc = (threadIdx.x & 7) * 8;
+    auto stage_load = [&](int j0, T (&v)[8]) {
+        const int j = j0 + sj;
 #pragma unroll
-        for (int ri = 0; ri < 2; ri++) av[ri] = FTl[(long long)j * Mpad + rowA + 16 * ri];
-#pragma unroll
-        for (int ci = 0; ci < 2; ci++) {
-            const int col = colB + 16 * ci;
-            bv[ci] = (j < sh.N && col < ncol && col != 1)
-                         ? noise[(long long)j * 2 * nlm + base + col]
-                         : T(0);
+        for (int e = 0; e < 8; e += 2) {
+            const int col = col0 + sc + e;  // even: (re, im) of m = col / 2
+            C2 w;
+            w.x = T(0);
+            w.y = T(0);
+            if (j < N && col < ncol)
+                w = gload(reinterpret_cast<const GLB C2 *>(noise + (long long)j * 2 * nlm + base + col));
+            v[e] = w.x;
+            v[e + 1] = col == 0 ? T(0) : w.y;  // Im of m = 0 is ignored
         }
+    };
+    auto stage_store = [&](int buf, const T (&v)[8]) {
 #pragma unroll
-        for (int ri = 0; ri < 2; ri++)
+        for (int e = 0; e < 8; e++) nz[buf][sj][sc + e] = v[e];
+    };
+
+    for (int q0 = 0; q0 < npairs; q0 += 4) {
+        const int q = q0 + wave;
+        const int tA = q, tB = RT - 1 - q;
+        const bool hasA = q < npairs, hasB = hasA && tB > tA;
+        // K-chunks this round needs: up to the largest tile of its first pair
+        const int kend = sh.lower ? min(Kpad, 32 * (RT - q0)) : Kpad;
+        const int nchunk = (kend + 31) / 32;
+        typename M::acc acc[2][2][4];
 #pragma unroll
-            for (int ci = 0; ci < 2; ci++) acc[ri][ci] = M::mfma(av[ri], bv[ci], acc[ri][ci]);
-    }
+        for (int a = 0; a < 2; a++)
 #pragma unroll
-    for (int ri = 0; ri < 2; ri++)
+            for (int h = 0; h < 2; h++)
 #pragma unroll
-        for (int ci = 0; ci < 2; ci++)
+                for (int c = 0; c < 4; c++) acc[a][h][c] = typename M::acc{};
+        // F^T fragments of a chunk: [tile][half][K-step]
+        T af[1][2][2][8];
+        auto load_a = [&](int c, T (&A)[2][2][8]) {
 #pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int row = row0 + 32 * wr + 16 * ri + M::row(k4, r);
-                const int col = colB + 16 * ci;
-                if (row < sh.N && col < ncol) {
-                    const int m = col >> 1;
-                    phi[mrow(sh.L, m, l) * sh.Cpad + 2 * row + (col & 1)] = acc[ri][ci][r];
+            for (int ks = 0; ks < 8; ks++) {
+                const int j = 32 * c + 4 * ks + k4;
+                const bool jv = j < Kpad;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    A[0][h][ks] = (hasA && jv) ? FTl[(long long)j * Mpad + 32 * tA + 16 * h + i16] : T(0);
+                    A[1][h][ks] = (hasB && jv) ? FTl[(long long)j * Mpad + 32 * tB + 16 * h + i16] : T(0);
                 }
             }
+        };
+        T v[8];
+        stage_load(0, v);
+        stage_store(0, v);
+        load_a(0, af[0]);
+        __syncthreads();
+        for (int c = 0; c < nchunk; c++) {
+            // MFMAs from LDS buffer c & 1 while the next chunk's noise rows
+            // load; the next chunk's F^T fragments load after the MFMAs
+            const int buf = c & 1;
+            const bool more = c + 1 < nchunk;
+            if (more) stage_load(32 * (c + 1), v);
+            const int j0 = 32 * c;
+            const bool useA = hasA && (!sh.lower || j0 < 32 * tA + 32);
+            const bool useB = hasB && (!sh.lower || j0 < 32 * tB + 32);
+#pragma unroll
+            for (int ks = 0; ks < 8; ks++) {
+                T bv[4];
+#pragma unroll
+                for (int cf = 0; cf < 4; cf++) bv[cf] = nz[buf][4 * ks + k4][16 * cf + i16];
+                if (useA) {
+#pragma unroll
+                    for (int h = 0; h < 2; h++)
+#pragma unroll
+                        for (int cf = 0; cf < 4; cf++)
+                            acc[0][h][cf] = M::mfma(af[0][0][h][ks], bv[cf], acc[0][h][cf]);
+                }
+                if (useB) {
+#pragma unroll
+                    for (int h = 0; h < 2; h++)
+#pragma unroll
+                        for (int cf = 0; cf < 4; cf++)
+                            acc[1][h][cf] = M::mfma(af[0][1][h][ks], bv[cf], acc[1][h][cf]);
+                }
+            }
+            if (more) {
+                stage_store(buf ^ 1, v);
+                load_a(c + 1, af[0]);
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int a = 0; a < 2; a++) {
+            const int t = a == 0 ? tA : tB;
+            if (!(a == 0 ? hasA : hasB)) continue;
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+#pragma unroll
+                for (int cf = 0; cf < 4; cf++)
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const int row = 32 * t + 16 * h + M::row(k4, r);
+                        const int col = col0 + 16 * cf + i16;
+                        if (row < N && col < ncol) {
+                            const int m = col >> 1;
+                            phi[mrow(sh.L, m, l) * sh.Cpad + 2 * row + (col & 1)] = acc[a][h][cf][r];
+                        }
+                    }
+        }
+    }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_filter(Shape sh, const T *__restrict__ FT, int Kpad,
+__global__ __launch_bounds__(256, filter_blocks<T>()) void k_filter(Shape sh, const T *__restrict__ FT, int Kpad,
                                                 int Mpad, const int2 *__restrict__ tiles,
                                                 const T *__restrict__ noise, T *__restrict__ phi)
 {
-    body_filter<T>(sh, FT, Kpad, Mpad, tiles, noise, phi, blockIdx.x, blockIdx.y);
+    body_filter<T>(sh, FT, Kpad, Mpad, tiles, noise, phi, blockIdx.x);
 }
 
 // ------------------------------------------------------- linear radial sum
@@ -138,19 +255,22 @@ __device__ inline void neumaier(double &s, double &c, double v)
 }
 
 template <typename T>
-__device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *__restrict__ V,
-                                                const T *__restrict__ noise,
-                                                double2 *__restrict__ aL, int bid)
+__device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *__restrict__ V_in,
+                                                const T *__restrict__ noise_in,
+                                                double2 *__restrict__ aL_in, int bid)
 {
+    auto *__restrict__ V = glb(V_in);
+    auto *__restrict__ noise = glb(noise_in);
+    auto *__restrict__ aL = glb(aL_in);
     const long long idx = (long long)bid * 256 + threadIdx.x;
     if (idx >= sh.nlm) return;
     const int l = l_of_index(idx);
     const bool m0 = lm_index(l, 0) == idx;
     double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
-    const double *VT = V + (long long)l * sh.N;
-    const double *VE = V + (long long)(sh.L + 1) * sh.N + (long long)l * sh.N;
+    const auto VT = V + (long long)l * sh.N;
+    const auto VE = V + (long long)(sh.L + 1) * sh.N + (long long)l * sh.N;
     for (int j = 0; j < sh.N; j++) {
-        const T *nz = noise + 2 * ((long long)j * sh.nlm + idx);
+        const auto nz = noise + 2 * ((long long)j * sh.nlm + idx);
         const double re = (double)nz[0];
         const double im = m0 ? 0.0 : (double)nz[1];
         neumaier(s[0], c[0], VT[j] * re);
@@ -158,8 +278,8 @@ __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *_
         neumaier(s[2], c[2], VE[j] * re);
         neumaier(s[3], c[3], VE[j] * im);
     }
-    aL[idx] = make_double2(s[0] + c[0], s[1] + c[1]);
-    aL[sh.nlm + idx] = make_double2(s[2] + c[2], s[3] + c[3]);
+    gstore(aL + idx, make_double2(s[0] + c[0], s[1] + c[1]));
+    gstore(aL + sh.nlm + idx, make_double2(s[2] + c[2], s[3] + c[3]));
 }
 
 template <typename T>
@@ -188,27 +308,35 @@ template <typename T> constexpr int synth_ld() { return sizeof(T) == 8 ? 36 : 72
 // MFMAs.  The wave starts at the first stored state below the first l where
 // any of its pairs has |lambda_lm| > 1e-30 (polar skip).
 template <typename T, int CF>
-__device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restrict__ tiles,
-                                           const double *__restrict__ x,
-                                           const double2 *__restrict__ seed,
-                                           const int *__restrict__ seedoff,
-                                           const int *__restrict__ lstart,
-                                           const double2 *__restrict__ coef,
-                                           const T *__restrict__ phi, T *__restrict__ G, int bid)
+__device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restrict__ tiles_in,
+                                           const double *__restrict__ x_in,
+                                           const double2 *__restrict__ seed_in,
+                                           const int *__restrict__ seedoff_in,
+                                           const int *__restrict__ lstart_in,
+                                           const double2 *__restrict__ coef_in,
+                                           const T *__restrict__ phi_in, T *__restrict__ G_in, int bid)
 {
+    auto *__restrict__ tiles = glb(tiles_in);
+    auto *__restrict__ x = glb(x_in);
+    auto *__restrict__ seed = glb(seed_in);
+    auto *__restrict__ seedoff = glb(seedoff_in);
+    auto *__restrict__ lstart = glb(lstart_in);
+    auto *__restrict__ coef = glb(coef_in);
+    auto *__restrict__ phi = glb(phi_in);
+    auto *__restrict__ G = glb(G_in);
     using M = Mt<T>;
     constexpr int PW = synth_pw<T>();
     constexpr int NF = PW / 16;
     constexpr int LD = synth_ld<T>();
     __shared__ T lamT[2][8][LD];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
-    const int4 tl = tiles[bid];
+    const int4 tl = gload(tiles + bid);
     if (tl.x < 0) return;  // idle slot of the XCD layout
     // wave-uniform: keeps the coefficient addresses scalar
     const int m = __builtin_amdgcn_readfirstlane(tl.x);
     const int pt = __builtin_amdgcn_readfirstlane(tl.y);
     const int ct = __builtin_amdgcn_readfirstlane(tl.z);
-    const double2 *__restrict__ cm_row = coef + crow(L, m);
+    const auto cm_row = coef + crow(L, m);
     const int lane = threadIdx.x;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int p0 = pt * PW;
@@ -224,7 +352,7 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
     const int u0 = ls <= L ? (ls - m) / kSeedStride : 0;
     double l1 = 0.0, l2 = 0.0;
     if (pv && ls <= L) {
-        const double2 st = seed[((long long)seedoff[m] + u0) * npair + p];
+        const double2 st = gload(seed + ((long long)seedoff[m] + u0) * npair + p);
         l1 = st.x;
         l2 = st.y;
     }
@@ -241,9 +369,9 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
     // B operands of a K-step: rows l0 + 2 k4 (even l - m) and l0 + 2 k4 + 1 (odd).
     // Rows past l = L belong to the next m (or to the zero padding after the
     // last one) and meet lambda = 0 exactly, so no per-lane bounds are needed.
-    const T *colbase = phi + rowm * Cpad + colb;
+    const auto colbase = phi + rowm * Cpad + colb;
     auto loadB = [&](int l0, T *E, T *O) {
-        const T *rE = colbase + (long long)(l0 + 2 * k4 - m) * Cpad;
+        const auto rE = colbase + (long long)(l0 + 2 * k4 - m) * Cpad;
 #pragma unroll
         for (int cf = 0; cf < CF; cf++) {
             E[cf] = rE[16 * cf];
@@ -261,7 +389,7 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
             for (int q = 0; q < 8; q++) {
                 // rows past L are the zero padding of m's coefficient block, so
                 // lambda = 0 there exactly
-                const double2 ab = cm_row[l0 + q - m];
+                const double2 ab = gload(cm_row + (l0 + q - m));
                 const double nv = ab.x * xp * l1 - ab.y * l2;
                 v[q] = nv;
                 l2 = l1;
@@ -320,8 +448,9 @@ __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restri
                     C2V v;
                     v.x = acc[f][0][cf][r];
                     v.y = acc[f][1][cf][r];
-                    *reinterpret_cast<C2V *>(
-                        G + ((((long long)pair * (L + 1) + m) * Cpad) + colb + 16 * cf) * 2) = v;
+                    gstore(reinterpret_cast<GLB C2V *>(
+                               G + ((((long long)pair * (L + 1) + m) * Cpad) + colb + 16 * cf) * 2),
+                           v);
                 }
             }
 }
@@ -565,7 +694,7 @@ __device__ inline int mod_p(int i, int p) { return (p & (p - 1)) == 0 ? (i & (p 
 __device__ __forceinline__ int rix(int j) { return j + (j >> 5); }
 
 template <typename C2, int R, bool INV, int NMAX>
-__device__ __forceinline__ void fft_pass(C2 *buf, int n, int p, const C2 *__restrict__ tw, int tid)
+__device__ __forceinline__ void fft_pass(C2 *buf, int n, int p, const GLB C2 *__restrict__ tw, int tid)
 {
     constexpr int MAXB = (NMAX / R + 255) / 256;
     const int nb = n / R;
@@ -578,7 +707,7 @@ __device__ __forceinline__ void fft_pass(C2 *buf, int n, int p, const C2 *__rest
         const int k = mod_p(tid, p);
 #pragma unroll
         for (int t = 1; t < R; t++) {
-            w0[t] = tw[t * k * tstep];
+            w0[t] = gload(tw + t * k * tstep);
             if (INV) w0[t].y = -w0[t].y;
         }
     }
@@ -597,7 +726,7 @@ __device__ __forceinline__ void fft_pass(C2 *buf, int n, int p, const C2 *__rest
                 const int k = mod_p(i, p);
 #pragma unroll
                 for (int t = 1; t < R; t++) {
-                    C2 w = tw[t * k * tstep];
+                    C2 w = gload(tw + t * k * tstep);
                     if (INV) w.y = -w.y;
                     xv[t] = cmul(xv[t], w);
                 }
@@ -624,7 +753,7 @@ __device__ __forceinline__ void fft_pass(C2 *buf, int n, int p, const C2 *__rest
 // Compile-time pass of radix R with stride P over an N-point ring: the same
 // Stockham step as fft_pass with every index folded to constants.
 template <typename C2, int R, bool INV, int N, int P>
-__device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw, int tid)
+__device__ __forceinline__ void fft_pass_c(C2 *buf, const GLB C2 *__restrict__ tw, int tid)
 {
     constexpr int NB = N / R;
     constexpr int TSTEP = N / (P * R);
@@ -635,7 +764,7 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw, i
         const int k = tid % P;
 #pragma unroll
         for (int t = 1; t < R; t++) {
-            w0[t] = tw[t * k * TSTEP];
+            w0[t] = gload(tw + t * k * TSTEP);
             if (INV) w0[t].y = -w0[t].y;
         }
     }
@@ -655,7 +784,7 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw, i
                     const int k = i % P;
 #pragma unroll
                     for (int t = 1; t < R; t++) {
-                        C2 w = tw[t * k * TSTEP];
+                        C2 w = gload(tw + t * k * TSTEP);
                         if (INV) w.y = -w.y;
                         xv[t] = cmul(xv[t], w);
                     }
@@ -681,7 +810,7 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const C2 *__restrict__ tw, i
 }
 
 template <typename C2, bool INV, int N, int P, int R, int... Rest>
-__device__ __forceinline__ void fft_static(C2 *buf, const C2 *__restrict__ tw, int tid)
+__device__ __forceinline__ void fft_static(C2 *buf, const GLB C2 *__restrict__ tw, int tid)
 {
     fft_pass_c<C2, R, INV, N, P>(buf, tw, tid);
     if constexpr (sizeof...(Rest) > 0) fft_static<C2, INV, N, P * R, Rest...>(buf, tw, tid);
@@ -693,7 +822,7 @@ __device__ __forceinline__ void fft_static(C2 *buf, const C2 *__restrict__ tw, i
 // rings run in the instantiation below it, and a plan longer than NMAX would
 // need more registers than the kernel reserves.
 template <typename C2, bool INV, int NMAX>
-__device__ __forceinline__ bool fft_planned(C2 *buf, int n, const C2 *__restrict__ tw, int tid)
+__device__ __forceinline__ bool fft_planned(C2 *buf, int n, const GLB C2 *__restrict__ tw, int tid)
 {
     if constexpr (NMAX == 1024) {
         if (n == 768) { fft_static<C2, INV, 768, 1, 16, 12, 4>(buf, tw, tid); return true; }
@@ -714,7 +843,7 @@ __device__ __forceinline__ bool fft_planned(C2 *buf, int n, const C2 *__restrict
 // compiled in, which keeps the register budget of the planned kernels to
 // what their passes need.
 template <typename C2, bool INV, int NMAX, bool PLANNED>
-__device__ __forceinline__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__restrict__ tw, int tid)
+__device__ __forceinline__ void fft_lds(C2 *buf, const Shape &sh, const GLB C2 *__restrict__ tw, int tid)
 {
     if constexpr (PLANNED) {
         (void)fft_planned<C2, INV, NMAX>(buf, sh.nphi, tw, tid);
@@ -748,11 +877,15 @@ __device__ __forceinline__ void fft_lds(C2 *buf, const Shape &sh, const C2 *__re
 // Blocks are numbered so that consecutive shell groups of one pair run on the
 // same XCD (shared L2 lines).
 template <typename T, int NMAX, int S, bool PLANNED>
-__device__ __forceinline__ void body_ring(const Shape &sh, const double *__restrict__ wq,
-                                          const typename Mt<T>::c2 *__restrict__ tw,
-                                          const T *__restrict__ G, T *__restrict__ F,
+__device__ __forceinline__ void body_ring(const Shape &sh, const double *__restrict__ wq_in,
+                                          const typename Mt<T>::c2 *__restrict__ tw_in,
+                                          const T *__restrict__ G_in, T *__restrict__ F_in,
                                           double *__restrict__ maps, int mode, int bid)
 {
+    auto *__restrict__ wq = glb(wq_in);
+    auto *__restrict__ tw = glb(tw_in);
+    auto *__restrict__ G = glb(G_in);
+    auto *__restrict__ F = glb(F_in);
     using C2 = typename Mt<T>::c2;
     using Q = typename Mt<T>::quad;
     extern __shared__ unsigned char smem_raw[];
@@ -771,7 +904,7 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
     const int io = threadIdx.x % S, mq = threadIdx.x / S;
     C2 *iob = reinterpret_cast<C2 *>(smem_raw) + io * npad;
     const bool iov = s0 + io < sh.N;
-    const T *Gp = G + ((long long)p * (L + 1) * Cpad + 2 * (s0 + io)) * 2;
+    const auto Gp = G + ((long long)p * (L + 1) * Cpad + 2 * (s0 + io)) * 2;
 
     // bins (L, n - L) are empty; the loop below writes every other bin
     for (int q = L + 1 + tid; q < n - L; q += 256) {
@@ -788,7 +921,7 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
     for (int k = 0; k < KM; k++) {
         const int m = mq + 256 * k;
         if (iov && m <= L)
-            v[k] = *reinterpret_cast<const Q *>(Gp + (long long)m * Cpad * 2);
+            v[k] = gload(reinterpret_cast<const GLB Q *>(Gp + (long long)m * Cpad * 2));
         else
             v[k] = Q{};
     }
@@ -833,14 +966,14 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
 
     const T wgt = (T)wq[p];
     const T half = T(0.5);
-    T *Fp = F + ((long long)p * Cpad + 2 * (s0 + io)) * 2;
+    const auto Fp = F + ((long long)p * Cpad + 2 * (s0 + io)) * 2;
     for (int m = mq; m <= L; m += 256) {
         const C2 W1 = iob[rix(m)];
         const C2 W2 = iob[rix(m == 0 ? 0 : n - m)];
         T Ar = half * (W1.x + W2.x), Ai = half * (W1.y - W2.y);
         T Br = half * (W1.y + W2.y), Bi = -half * (W1.x - W2.x);
         if (sh.alias && m == L && iov) {
-            const Q v = *reinterpret_cast<const Q *>(Gp + (long long)L * Cpad * 2);
+            const Q v = gload(reinterpret_cast<const GLB Q *>(Gp + (long long)L * Cpad * 2));
             const T Er = v.x, Or = v.y, Ei = v.z, Oi = v.w;
             T Nr = Er + Or, Ni = Ei + Oi, Sr = Er - Or, Si = Ei - Oi;
             if (eq) Sr = Si = T(0);
@@ -858,7 +991,7 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
         f.w = wgt * (Ai - Bi);  // O im
         if (eq) f.y = f.w = T(0);
         if (m == 0) f.z = f.w = T(0);
-        if (iov) *reinterpret_cast<Q *>(Fp + (long long)m * sh.npair * Cpad * 2) = f;
+        if (iov) gstore(reinterpret_cast<GLB Q *>(Fp + (long long)m * sh.npair * Cpad * 2), f);
     }
 }
 
@@ -896,32 +1029,45 @@ static_assert(kCoefPad >= anal_rw<float>() && kCoefPad >= anal_rw<double>(), "co
 // mode 1 writes Phi_NL per shell; mode 2 (reverse pass) writes the per-shell
 // output plus the direct cotangent sum_X W^X_ls abar^X_lm, no mean handling.
 template <typename T, int CF, int MODE>
-__device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restrict__ tiles,
-                                          const double *__restrict__ x,
-                                          const double2 *__restrict__ coef,
-                                          const double2 *__restrict__ seed,
-                                          const int *__restrict__ seedoff,
-                                          const int *__restrict__ cmin,
-                                          const double *__restrict__ W,
-                                          const double *__restrict__ mu,
-                                          const T *__restrict__ F, double2 *__restrict__ part,
-                                          T *__restrict__ outphi,
-                                          const double2 *__restrict__ gT,
-                                          const double2 *__restrict__ gE, int bid)
+__device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restrict__ tiles_in,
+                                          const double *__restrict__ x_in,
+                                          const double2 *__restrict__ coef_in,
+                                          const double2 *__restrict__ seed_in,
+                                          const int *__restrict__ seedoff_in,
+                                          const int *__restrict__ cmin_in,
+                                          const double *__restrict__ W_in,
+                                          const double *__restrict__ mu_in,
+                                          const T *__restrict__ F_in, double2 *__restrict__ part_in,
+                                          T *__restrict__ outphi_in,
+                                          const double2 *__restrict__ gT_in,
+                                          const double2 *__restrict__ gE_in, int bid)
 {
+    auto *__restrict__ tiles = glb(tiles_in);
+    auto *__restrict__ x = glb(x_in);
+    auto *__restrict__ coef = glb(coef_in);
+    auto *__restrict__ seed = glb(seed_in);
+    auto *__restrict__ seedoff = glb(seedoff_in);
+    auto *__restrict__ cmin = glb(cmin_in);
+    auto *__restrict__ W = glb(W_in);
+    auto *__restrict__ mu = glb(mu_in);
+    auto *__restrict__ F = glb(F_in);
+    auto *__restrict__ part = glb(part_in);
+    auto *__restrict__ outphi = glb(outphi_in);
+    auto *__restrict__ gT = glb(gT_in);
+    auto *__restrict__ gE = glb(gE_in);
     using M = Mt<T>;
     constexpr int RW = anal_rw<T>();
     constexpr int NF = RW / 32;
     constexpr int LD = anal_ld<T>();
     __shared__ T lam[RW][LD];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
-    const int4 tl = tiles[bid];
+    const int4 tl = gload(tiles + bid);
     if (tl.x < 0) return;  // idle slot of the XCD layout
     // wave-uniform: keeps the coefficient addresses scalar
     const int m = __builtin_amdgcn_readfirstlane(tl.x);
     const int lt = __builtin_amdgcn_readfirstlane(tl.y);
     const int ct = __builtin_amdgcn_readfirstlane(tl.z);
-    const double2 *__restrict__ cm_row = coef + crow(L, m);
+    const auto cm_row = coef + crow(L, m);
     const int lane = threadIdx.x;
     const int i16 = lane & 15, k4 = lane >> 4;
     const int half = lane >> 5, pl = lane & 31;
@@ -951,13 +1097,13 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
         // ahead; pairs past the last one read the next m (or the zero padding
         // after the last m) and meet lambda = 0 exactly
         // F[m][pair][column] holds (E, O) interleaved
-        const T *fbase = F + (((long long)m * npair + pc * kAnalPC + k4) * Cpad + colb) * 2;
+        const auto fbase = F + (((long long)m * npair + pc * kAnalPC + k4) * Cpad + colb) * 2;
         T fE[CF], fO[CF], gE_[CF], gO_[CF];
         auto loadF = [&](int kk, T *E, T *O) {
-            const T *f = fbase + (long long)(4 * kk) * Cpad * 2;
+            const auto f = fbase + (long long)(4 * kk) * Cpad * 2;
 #pragma unroll
             for (int cf = 0; cf < CF; cf++) {
-                const typename M::c2v v = *reinterpret_cast<const typename M::c2v *>(f + 32 * cf);
+                const typename M::c2v v = gload(reinterpret_cast<const GLB typename M::c2v *>(f + 32 * cf));
                 E[cf] = v.x;
                 O[cf] = v.y;
             }
@@ -968,7 +1114,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
             const bool pv = hact && p < npair;
             double a1 = 0.0, a0 = 0.0, xp = 0.0;  // lambda_{l-1}, lambda_{l-2}
             if (pv) {
-                const double2 sd = seed[srow * npair + p];
+                const double2 sd = gload(seed + srow * npair + p);
                 a1 = sd.x;
                 a0 = sd.y;
                 xp = x[p];
@@ -979,7 +1125,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
             for (int q = 0; q < RW / 2; q++) {
                 const int lA = l0w + q, lB = l0w + RW / 2 + q;
                 // rows past l = L read the zero padding of m's block
-                const double2 cA = cm_row[lA - m], cB = cm_row[lB - m];
+                const double2 cA = gload(cm_row + (lA - m)), cB = gload(cm_row + (lB - m));
                 const double2 ab = half ? cB : cA;
                 const double v = ab.x * xp * a1 - ab.y * a0;
                 lam[half * (RW / 2) + q][pl] = (T)v;
@@ -1034,7 +1180,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                     if (MODE == 2) {
                         if (lok) {
                             const long long id = lm_index(l, m);
-                            const double2 t = gT[id], e = gE[id];
+                            const double2 t = gload(gT + id), e = gload(gE + id);
                             const double wt = W[(long long)l * Npad + s];
                             const double we = W[(long long)(L + 1 + l) * Npad + s];
                             v += (col & 1) ? (m == 0 ? 0.0 : wt * t.y + we * e.y)
@@ -1068,10 +1214,10 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                     sE += __shfl_xor(sE, 8);
                     if (lok && i16 < 2) {
                         const long long id = lm_index(l, m);
-                        double *pT =
-                            reinterpret_cast<double *>(part + ((long long)ct * 2) * sh.nlm + id);
-                        double *pE =
-                            reinterpret_cast<double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
+                        GLB double *pT =
+                            reinterpret_cast<GLB double *>(part + ((long long)ct * 2) * sh.nlm + id);
+                        GLB double *pE =
+                            reinterpret_cast<GLB double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
                         pT[i16] = (m == 0 && i16 == 1) ? 0.0 : sT;
                         pE[i16] = (m == 0 && i16 == 1) ? 0.0 : sE;
                     }
@@ -1102,12 +1248,18 @@ __global__ __launch_bounds__(64, anal_waves<T>()) void k_anal(Shape sh, const in
 
 // -------------------------------------------------------------- combine
 
-__device__ __forceinline__ void body_combine(const Shape &sh, const double2 *__restrict__ part,
-                                             const double2 *__restrict__ aL, double fnl,
-                                             double2 *__restrict__ aT, double2 *__restrict__ aE,
-                                             double2 *__restrict__ aTn, double2 *__restrict__ aEn,
+__device__ __forceinline__ void body_combine(const Shape &sh, const double2 *__restrict__ part_in,
+                                             const double2 *__restrict__ aL_in, double fnl,
+                                             double2 *__restrict__ aT_in, double2 *__restrict__ aE_in,
+                                             double2 *__restrict__ aTn_in, double2 *__restrict__ aEn_in,
                                              int bid)
 {
+    auto *__restrict__ part = glb(part_in);
+    auto *__restrict__ aL = glb(aL_in);
+    auto *__restrict__ aT = glb(aT_in);
+    auto *__restrict__ aE = glb(aE_in);
+    auto *__restrict__ aTn = glb(aTn_in);
+    auto *__restrict__ aEn = glb(aEn_in);
     const long long idx = (long long)bid * 256 + threadIdx.x;
     if (idx >= sh.nlm) return;
     const int l = l_of_index(idx);
@@ -1116,19 +1268,19 @@ __device__ __forceinline__ void body_combine(const Shape &sh, const double2 *__r
     for (int X = 0; X < 2; X++) {
         double sr = 0, cr = 0, si = 0, ci = 0;
         for (int ct = 0; ct < sh.nct; ct++) {
-            const double2 v = part[((long long)ct * 2 + X) * sh.nlm + idx];
+            const double2 v = gload(part + ((long long)ct * 2 + X) * sh.nlm + idx);
             neumaier(sr, cr, v.x);
             neumaier(si, ci, v.y);
         }
         double2 nl = make_double2(sr + cr, m0 ? 0.0 : si + ci);
-        const double2 lin = aL[(long long)X * sh.nlm + idx];
+        const double2 lin = gload(aL + (long long)X * sh.nlm + idx);
         double2 tot = make_double2(lin.x + fnl * nl.x, m0 ? 0.0 : lin.y + fnl * nl.y);
         if (X == 0) {
-            aT[idx] = tot;
-            if (aTn) aTn[idx] = nl;
+            gstore(aT + idx, tot);
+            if (aTn) gstore(aTn + idx, nl);
         } else {
-            aE[idx] = tot;
-            if (aEn) aEn[idx] = nl;
+            gstore(aE + idx, tot);
+            if (aEn) gstore(aEn + idx, nl);
         }
     }
 }
@@ -1177,17 +1329,16 @@ __global__ __launch_bounds__(256) void g_radial_lin(const GroupItem *__restrict_
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void g_filter(const GroupItem *__restrict__ it,
+__global__ __launch_bounds__(256, filter_blocks<T>()) void g_filter(const GroupItem *__restrict__ it,
                                                 const int *__restrict__ ord,
                                                 const int *__restrict__ off, int n)
 {
     int lb;
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
-    const int nx = g.b.nk1;
-    if (lb >= nx * (g.b.Mpad / 64)) return;
+    if (lb >= g.b.nk1) return;
     body_filter<T>(g.sh, (const T *)g.b.FT, g.b.Kpad, g.b.Mpad, g.b.k1tiles, (const T *)g.noise,
-                   (T *)g.b.phi, lb % nx, lb / nx);
+                   (T *)g.b.phi, lb);
 }
 
 template <typename T, int CF>
@@ -1408,8 +1559,8 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         }
     }
     __syncthreads();
-    fft_lds<C2, true, NMAX, PLANNED>(b1, sh, tw, tid);
-    fft_lds<C2, true, NMAX, PLANNED>(b2, sh, tw, tid);
+    fft_lds<C2, true, NMAX, PLANNED>(b1, sh, glb(tw), tid);
+    fft_lds<C2, true, NMAX, PLANNED>(b2, sh, glb(tw), tid);
     const T wpix = (T)wq[p];
     const T two_f = (T)(2.0 * fnl);
     double fb = 0.0;
@@ -1449,7 +1600,7 @@ __global__ __launch_bounds__(256) void k_ring_adj(Shape sh, const double *__rest
         __syncthreads();
     }
     if (tid == 0) fpart[(long long)p * sh.N + s] = red[0];
-    fft_lds<C2, false, NMAX, PLANNED>(b1, sh, tw, tid);
+    fft_lds<C2, false, NMAX, PLANNED>(b1, sh, glb(tw), tid);
     const T half = T(0.5);
     for (int m = tid; m <= L; m += 256) {
         const C2 W1 = b1[rix(m)];
@@ -1595,7 +1746,7 @@ hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s)
 hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
                          hipStream_t s)
 {
-    dim3 grid(b.nk1, b.Mpad / 64);
+    dim3 grid(b.nk1);
     if (sh.fp32)
         hipLaunchKernelGGL(k_filter<float>, grid, dim3(256), 0, s, sh, (const float *)b.FT, b.Kpad,
                            b.Mpad, b.k1tiles, (const float *)noise, (float *)phi_out);
@@ -1848,7 +1999,7 @@ long long group_blocks(int stage, const Shape &sh, const Bufs &b)
     switch (stage) {
     case GS_RADIAL_LIN:
     case GS_COMBINE: return (sh.nlm + 255) / 256;
-    case GS_FILTER: return (long long)b.nk1 * (b.Mpad / 64);
+    case GS_FILTER: return b.nk1;
     case GS_SYNTH: return b.nk2;
     case GS_RING: {
         const int S = ring_shells(sh.fp32);

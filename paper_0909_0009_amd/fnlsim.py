@@ -225,6 +225,48 @@ class Simulator:
         return out
 
 
+class Batch:
+    """Contexts of one precision and stream (uneven lmax and node counts)
+    whose forward passes run as one grouped launch per stage, captured in a
+    HIP graph on the first call (sim_batch_create / sim_batch_forward)."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        arr = (ctypes.c_void_p * len(self.sims))(*[s.handle.value for s in self.sims])
+        h = ctypes.c_void_p()
+        _check(lib().sim_batch_create(arr, len(self.sims), ctypes.byref(h)), None)
+        self._h = h
+
+    def forward(self, noises, fnls, outs=None):
+        """noises: one [N_i][n_lm_i] CUDA tensor per context; fnls: one per
+        context.  Returns (or fills) [(aT_i, aE_i)], each [1][n_lm_i] complex128."""
+        n = len(self.sims)
+        if len(noises) != n or len(fnls) != n:
+            raise ValueError(f"need {n} noises and fnls")
+        noises = [s._noise(x) for s, x in zip(self.sims, noises)]
+        if outs is None:
+            outs = [(torch.empty((1, s.n_lm), dtype=torch.complex128, device=x.device),
+                     torch.empty((1, s.n_lm), dtype=torch.complex128, device=x.device))
+                    for s, x in zip(self.sims, noises)]
+        nz = (ctypes.c_void_p * n)(*[x.data_ptr() for x in noises])
+        aT = (ctypes.c_void_p * n)(*[o[0].data_ptr() for o in outs])
+        aE = (ctypes.c_void_p * n)(*[o[1].data_ptr() for o in outs])
+        f = np.ascontiguousarray(fnls, dtype=np.float64)
+        _check(lib().sim_batch_forward(self._h, nz, f.ctypes.data, aT, aE), None)
+        return outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sim_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class FnlSimFunction(torch.autograd.Function):
     """(noise, fnl) -> (aT, aE) with the hand-written adjoint as backward.
     noise: [R][N][n_lm] complex CUDA tensor; fnl: [R] float64 tensor."""

@@ -157,23 +157,70 @@ def sph_bessel_table(L, x):
 
 # ------------------------------------------------------------- covariance
 
-def covariance(L, r, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=4096, kchunk=64):
+# The k quadrature is summed in KGROUPS fixed contiguous groups of k chunks,
+# each group in order, then the group sums in order: the result does not
+# depend on how many worker threads evaluate the groups.
+KGROUPS = 8
+
+
+def _cov_group(L, r, k, D, q0s, kchunk):
+    N = r.size
+    C = np.zeros((L + 1, N, N))
+    for q0 in q0s:
+        kc = k[q0:q0 + kchunk]
+        x = np.outer(r, kc)                       # [N, kc]
+        J = sph_bessel_table(L, x.ravel()).reshape(L + 1, N, kc.size)
+        JD = J * D[q0:q0 + kchunk][None, None, :]
+        C += np.matmul(JD, J.transpose(0, 2, 1))
+    return C
+
+
+def _cov_group_task(args):
+    return _cov_group(*args)
+
+
+def input_workers():
+    """Worker threads for input generation (FNLSIM_INPUT_WORKERS, else the
+    usable cores, at most KGROUPS)."""
+    env = os.environ.get("FNLSIM_INPUT_WORKERS")
+    if env:
+        return max(1, int(env))
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    return max(1, min(KGROUPS, ncpu))
+
+
+def covariance(L, r, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=4096, kchunk=64, workers=None):
     """C_l(r_i, r_j) for l = 0..L, shape [L+1, N, N] (Eq. cov_phi)."""
     r = np.asarray(r, dtype=np.float64)
-    N = r.size
     k = np.geomspace(kmin, kmax, nk)
     h = math.log(kmax / kmin) / (nk - 1)
     dlnk = np.full(nk, h)
     dlnk[0] = dlnk[-1] = 0.5 * h
     # dk k^2 P(k) = dlnk * A (k/0.05)^(ns-1);  prefactor 2/pi
     D = (2.0 / math.pi) * A * (k / 0.05) ** (ns - 1.0) * dlnk
-    C = np.zeros((L + 1, N, N))
-    for q0 in range(0, nk, kchunk):
-        kc = k[q0:q0 + kchunk]
-        x = np.outer(r, kc)                       # [N, kc]
-        J = sph_bessel_table(L, x.ravel()).reshape(L + 1, N, kc.size)
-        JD = J * D[q0:q0 + kchunk][None, None, :]
-        C += np.matmul(JD, J.transpose(0, 2, 1))
+    starts = list(range(0, nk, kchunk))
+    per = -(-len(starts) // KGROUPS)
+    groups = [starts[g * per:(g + 1) * per] for g in range(KGROUPS)]
+    groups = [g for g in groups if g]
+    tasks = [(L, r, k, D, g, kchunk) for g in groups]
+    workers = input_workers() if workers is None else workers
+    # threads (numpy releases the GIL inside its array loops); every matmul
+    # runs on one BLAS thread, so the sums do not depend on the thread count
+    import concurrent.futures
+
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1, user_api="blas"):
+        if workers > 1 and len(tasks) > 1:
+            with concurrent.futures.ThreadPoolExecutor(min(workers, len(tasks))) as ex:
+                parts = list(ex.map(_cov_group_task, tasks))
+        else:
+            parts = [_cov_group_task(t) for t in tasks]
+    C = parts[0]
+    for P in parts[1:]:
+        C += P
     return C
 
 
@@ -247,7 +294,7 @@ def _cache_dir():
 
 def problem(L, N, seed=TRANSFER_SEED, cache=True):
     """dict(r, w, filter, alpha, beta, cov) for band limit L and N nodes."""
-    key = hashlib.sha1(f"v1|{L}|{N}|{seed}".encode()).hexdigest()[:16]
+    key = hashlib.sha1(f"v2|{L}|{N}|{seed}".encode()).hexdigest()[:16]
     path = os.path.join(_cache_dir(), f"problem_L{L}_N{N}_{key}.npz") if cache else None
     if path and os.path.exists(path):
         with np.load(path, allow_pickle=False) as z:
