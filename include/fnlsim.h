@@ -86,6 +86,9 @@ typedef struct {
     int mean_mode;  /* SIM_MEAN_SAMPLE or SIM_MEAN_ENSEMBLE                        */
     int max_batch;  /* reserved; 0                                                 */
     void *stream;   /* hipStream_t for every launch; NULL = default stream         */
+    int tune;       /* 0: column tile of 16 CF columns with CF in 1..5 chosen to
+                       minimise padding; 1: time one forward pass (zero noise)
+                       for every CF at set-up and keep the fastest              */
 } sim_opts;
 
 /* Read-only facts about a context. */
@@ -93,6 +96,7 @@ typedef struct {
     int lmax, nshell, n_ring, n_phi, n_pair, precision, mean_mode;
     long long n_lm;
     long long workspace_bytes;  /* device memory owned by the context          */
+    int col_tile;               /* columns per matrix-core tile (16 CF)        */
 } sim_info;
 
 /* Create a context for band limit lmax and nshell radial nodes.
@@ -108,7 +112,9 @@ typedef struct {
  * are formed in FP64 here.  Returns SIM_EINVAL (no HIP call made) for
  * lmax < 1, nshell < 1, null pointers, non-finite values or a grid that is
  * too small; SIM_ENOMEM / SIM_EDEVICE if device set-up fails (*out is then
- * NULL). */
+ * NULL).  With opts->tune the call builds the context once per column tile,
+ * runs it, and keeps the fastest (set-up takes correspondingly longer; the
+ * results of every choice agree to rounding). */
 int sim_init(sim_ctx **out, int lmax, int nshell,
              const double *r, const double *w, const double *filter,
              const double *alpha, const double *beta, const sim_opts *opts);

@@ -288,17 +288,14 @@ int build_precision_tables(sim_ctx *c, const double *filter)
     return SIM_OK;
 }
 
-}  // namespace
+int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
+                double2 *aTn, double2 *aEn);
 
-extern "C" {
-
-int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double *w,
-             const double *filter, const double *alpha, const double *beta, const sim_opts *opts)
+// Build a context; force_cf = 0 picks the column tile by the padding rule.
+int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double *w,
+             const double *filter, const double *alpha, const double *beta, const sim_opts &o,
+             int force_cf)
 {
-    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
-    *out = nullptr;
-    sim_opts o{};
-    if (opts) o = *opts;
     if (lmax < 1 || lmax > 4096) return fail(nullptr, SIM_EINVAL, "lmax %d outside [1, 4096]", lmax);
     if (nshell < 1 || nshell > 4096)
         return fail(nullptr, SIM_EINVAL, "nshell %d outside [1, 4096]", nshell);
@@ -339,7 +336,9 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     sh.L = L;
     sh.N = N;
     sh.C = 2 * N;
-    {
+    if (force_cf) {
+        sh.CF = force_cf;
+    } else {
         int best = 1, bestpad = 1 << 30;
         for (int cf = 5; cf >= 1; cf--) {
             const int ct = 16 * cf;
@@ -448,10 +447,8 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     // which read the same F_m columns
     std::vector<int4> k2, k4;
     {
-        // pairs per synthesis wave: 64 (FP32) or 32 (FP64)
-        const int pw = sh.fp32 ? 64 : 32;
-        // l rows per analysis wave: 128 (FP32) or 64 (FP64)
-        const int rw = sh.fp32 ? 128 : 64;
+        const int pw = sh.fp32 ? fnl::kSynthPairsF32 : fnl::kSynthPairsF64;
+        const int rw = sh.fp32 ? fnl::kAnalRowsF32 : fnl::kAnalRowsF64;
         const int npt = (np + pw - 1) / pw;
         std::vector<std::vector<int4>> g2, g4;
         std::vector<double> w2, w4;
@@ -535,6 +532,75 @@ bad:
     return rc;
 }
 
+// Milliseconds of one forward pass of c on zero noise (after one warm-up), or
+// a negative value if it could not be measured.
+double time_forward(sim_ctx *c)
+{
+    const size_t elem = c->sh.fp32 ? sizeof(float2) : sizeof(double2);
+    void *noise = nullptr, *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    double ms = -1.0;
+    if (hipMalloc(&noise, elem * (size_t)c->sh.N * c->sh.nlm) == hipSuccess &&
+        hipMalloc(&out, sizeof(double2) * 2 * (size_t)c->sh.nlm) == hipSuccess &&
+        hipMemsetAsync(noise, 0, elem * (size_t)c->sh.N * c->sh.nlm, c->stream) == hipSuccess &&
+        hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
+        double2 *aT = (double2 *)out, *aE = aT + c->sh.nlm;
+        if (forward_one(c, noise, 0.0, aT, aE, nullptr, nullptr) == SIM_OK &&
+            hipEventRecord(e0, c->stream) == hipSuccess &&
+            forward_one(c, noise, 0.0, aT, aE, nullptr, nullptr) == SIM_OK &&
+            hipEventRecord(e1, c->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, e0, e1) == hipSuccess) ms = t;
+        }
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (noise) (void)hipFree(noise);
+    if (out) (void)hipFree(out);
+    return ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double *w,
+             const double *filter, const double *alpha, const double *beta, const sim_opts *opts)
+{
+    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    sim_opts o{};
+    if (opts) o = *opts;
+    if (o.tune != 0 && o.tune != 1) return fail(nullptr, SIM_EINVAL, "tune must be 0 or 1");
+    if (!o.tune) return init_ctx(out, lmax, nshell, r, w, filter, alpha, beta, o, 0);
+    // column-tile autotuner: one context per CF, the fastest is kept
+    sim_ctx *best = nullptr;
+    double best_ms = 0.0;
+    for (int cf = 5; cf >= 1; cf--) {
+        sim_ctx *c = nullptr;
+        const int rc = init_ctx(&c, lmax, nshell, r, w, filter, alpha, beta, o, cf);
+        if (rc) {
+            if (best) sim_destroy(best);
+            return rc;
+        }
+        const double ms = time_forward(c);
+        if (ms < 0.0) {
+            sim_destroy(c);
+            if (best) sim_destroy(best);
+            return fail(nullptr, SIM_EDEVICE, "column-tile tuning: a timed forward pass failed");
+        }
+        if (!best || ms < best_ms) {
+            if (best) sim_destroy(best);
+            best = c;
+            best_ms = ms;
+        } else {
+            sim_destroy(c);
+        }
+    }
+    *out = best;
+    return SIM_OK;
+}
+
 int sim_destroy(sim_ctx *c)
 {
     if (!c) return SIM_OK;
@@ -562,6 +628,7 @@ int sim_get_info(const sim_ctx *c, sim_info *info)
     info->mean_mode = c->sh.mean_mode;
     info->n_lm = c->sh.nlm;
     info->workspace_bytes = c->ws_bytes;
+    info->col_tile = c->sh.CT;
     return SIM_OK;
 }
 
@@ -598,8 +665,9 @@ static int prof_mark(sim_ctx *c, int stage)
         if ((rc_ = prof_mark((ctx), -1))) return rc_; \
     } while (0)
 
-static int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
-                       double2 *aTn, double2 *aEn)
+namespace {
+int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
+                double2 *aTn, double2 *aEn)
 {
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
@@ -612,6 +680,7 @@ static int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, d
     STAGE(c, 5, fnl::launch_combine(sh, b, fnl, aT, aE, aTn, aEn, s));
     return SIM_OK;
 }
+}  // namespace
 
 int sim_profile(sim_ctx *c, int enable)
 {

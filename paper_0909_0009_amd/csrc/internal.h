@@ -14,6 +14,10 @@ constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
 constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)
 constexpr int kCoefPad = 128;      // zero rows after each m's coefficient block (>= analysis rows per block)
 constexpr int kPhiPad = 32;        // zero rows after the last m block of the Phi matrices (synthesis prefetch)
+// Work of one Legendre wave: ring pairs per synthesis wave and l rows per
+// analysis wave (FP32 / FP64; register budget of the accumulators).
+constexpr int kSynthPairsF32 = 64, kSynthPairsF64 = 32;
+constexpr int kAnalRowsF32 = 64, kAnalRowsF64 = 64;
 
 // Everything a kernel needs to know about the problem's shape.
 struct Shape {
@@ -133,9 +137,9 @@ hipError_t prepare_group_ring(int fp32, int nphi, int planned);
 
 // ----- launchers (kernels.hip); all asynchronous on `s`.
 hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);  // seeds, lstart, cmin
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);
 hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
                          hipStream_t s);
-hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);
 hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
                         hipStream_t s);
 // mode 0: square minus mean and forward transform into F; 1: write maps.

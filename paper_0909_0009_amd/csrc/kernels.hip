@@ -294,7 +294,7 @@ __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__re
 
 // Pairs per synthesis wave: 64 in FP32, 32 in FP64 (register budget of the
 // accumulators).  A synthesis workgroup is one wave.
-template <typename T> constexpr int synth_pw() { return sizeof(T) == 8 ? 32 : 64; }
+template <typename T> constexpr int synth_pw() { return sizeof(T) == 8 ? kSynthPairsF64 : kSynthPairsF32; }
 // LDS row stride of the transposed lambda tile (FP32: rows 2k apart land in
 // disjoint bank quarters, so the A-fragment reads are conflict-free)
 template <typename T> constexpr int synth_ld() { return sizeof(T) == 8 ? 36 : 72; }
@@ -1009,10 +1009,9 @@ __global__ __launch_bounds__(256 * ring_s<T>()) void k_ring(Shape sh, const doub
 
 // --------------------------------------------------------- Legendre analysis
 
-// Rows per analysis wave: 128 in FP32, 64 in FP64 (register budget of the
-// accumulators); pairs per chunk; LDS row strides that keep the A-fragment
-// reads free of bank conflicts.
-template <typename T> constexpr int anal_rw() { return sizeof(T) == 8 ? 64 : 128; }
+// Rows per analysis wave (kAnalRowsF32 / kAnalRowsF64); pairs per chunk; LDS
+// row strides that keep the A-fragment reads free of bank conflicts.
+template <typename T> constexpr int anal_rw() { return sizeof(T) == 8 ? kAnalRowsF64 : kAnalRowsF32; }
 template <typename T> constexpr int anal_ld() { return sizeof(T) == 8 ? 33 : 34; }
 constexpr int kAnalPC = 32;
 static_assert(kCoefPad >= anal_rw<float>() && kCoefPad >= anal_rw<double>(), "coefficient padding");

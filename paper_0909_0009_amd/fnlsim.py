@@ -39,14 +39,14 @@ class SimError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("n_ring", ctypes.c_int), ("n_phi", ctypes.c_int), ("precision", ctypes.c_int),
                 ("mean_mode", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("stream", ctypes.c_void_p)]
+                ("stream", ctypes.c_void_p), ("tune", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("lmax", ctypes.c_int), ("nshell", ctypes.c_int), ("n_ring", ctypes.c_int),
                 ("n_phi", ctypes.c_int), ("n_pair", ctypes.c_int), ("precision", ctypes.c_int),
                 ("mean_mode", ctypes.c_int), ("n_lm", ctypes.c_longlong),
-                ("workspace_bytes", ctypes.c_longlong)]
+                ("workspace_bytes", ctypes.c_longlong), ("col_tile", ctypes.c_int)]
 
 
 _lib = None
@@ -109,7 +109,7 @@ class Simulator:
     """One context of the map generator (see include/fnlsim.h)."""
 
     def __init__(self, lmax, r, w, filt, alpha, beta, n_ring=0, n_phi=0, precision="fp64",
-                 mean="sample", stream=None):
+                 mean="sample", stream=None, tune=False):
         self.lmax = int(lmax)
         r, w, filt, alpha, beta = map(_f64, (r, w, filt, alpha, beta))
         self.nshell = int(r.shape[0])
@@ -122,7 +122,7 @@ class Simulator:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = _Opts(int(n_ring), int(n_phi), _PRECISION[precision], _MEAN[mean], 0,
-                     ctypes.c_void_p(stream) if stream else None)
+                     ctypes.c_void_p(stream) if stream else None, 1 if tune else 0)
         h = ctypes.c_void_p()
         rc = lib().sim_init(ctypes.byref(h), L, N, r.ctypes.data, w.ctypes.data,
                             filt.ctypes.data, alpha.ctypes.data, beta.ctypes.data,
@@ -134,6 +134,7 @@ class Simulator:
         self.n_ring, self.n_phi, self.n_pair = info.n_ring, info.n_phi, info.n_pair
         self.n_lm = int(info.n_lm)
         self.workspace_bytes = int(info.workspace_bytes)
+        self.col_tile = int(info.col_tile)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -177,3 +177,24 @@ def test_dense_filter(fs, orc, precision):
     got = sim.forward(_dev(noise, precision), 60.0, want_nl=True)
     ref = orc.Problem(L, p["r"], p["w"], F, p["alpha"], p["beta"]).forward(noise, 60.0)
     _check_all(got, ref, L, TOL[precision], f"dense filter {precision}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_tuned_column_tile(fs, orc, precision):
+    """The set-up autotuner (one context per column tile, fastest kept) gives
+    the oracle's result, and the untuned context's to rounding."""
+    L, N = 40, 33
+    p = _problem(L, N)
+    tuned = _sim(fs, p, L, precision, tune=True)
+    plain = _sim(fs, p, L, precision)
+    assert tuned.col_tile in (16, 32, 48, 64, 80) and plain.col_tile in (16, 32, 48, 64, 80)
+    noise = inputs.noise(L, N, 77)
+    if precision == "fp32":
+        noise = noise.astype(np.complex64).astype(np.complex128)
+    got = tuned.forward(_dev(noise, precision), 40.0, want_nl=True)
+    ref = _oracle(orc, p, L).forward(noise, 40.0)
+    _check_all(got, ref, L, TOL[precision], f"tuned (tile {tuned.col_tile}) {precision}")
+    base = plain.forward(_dev(noise, precision), 40.0, want_nl=True)
+    for g, b in zip(got, base):
+        assert_close(g.cpu().numpy().reshape(-1), b.cpu().numpy().reshape(-1), L,
+                     1e-12 if precision == "fp64" else 1e-6, "tuned vs untuned")
