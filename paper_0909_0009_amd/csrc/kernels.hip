@@ -774,8 +774,15 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const GLB C2 *__restrict__ t
         const int i = tid + c * 256;
         if (NB % 256 == 0 || i < NB) {
             C2 xv[R];
+            if constexpr (NB % 32 == 0) {
+                // t NB is a multiple of 32: leg t sits a fixed distance from leg 0
+                const C2 *b0 = buf + rix(i);
 #pragma unroll
-            for (int t = 0; t < R; t++) xv[t] = buf[rix(i + t * NB)];
+                for (int t = 0; t < R; t++) xv[t] = b0[t * (NB + NB / 32)];
+            } else {
+#pragma unroll
+                for (int t = 0; t < R; t++) xv[t] = buf[rix(i + t * NB)];
+            }
             if constexpr (P > 1) {
                 if constexpr (SHARED_K) {
 #pragma unroll
@@ -802,8 +809,24 @@ __device__ __forceinline__ void fft_pass_c(C2 *buf, const GLB C2 *__restrict__ t
         if (NB % 256 == 0 || i < NB) {
             const int k = i % P;
             const int j = (i - k) * R + k;
+            C2 *b0 = buf + rix(j);
+            // padded position of j + t P as rix(j) + a compile-time offset:
+            //  P % 32 == 0: t P shifts by whole pad groups;
+            //  P == 1, R | 32: j is a multiple of R, j + t stays in j's group;
+            //  P == 16, R even: j % 32 = k < 16, so (j + 16 t) / 32 = j / 32 + t / 2
+            if constexpr (P % 32 == 0) {
 #pragma unroll
-            for (int t = 0; t < R; t++) buf[rix(j + t * P)] = y[c][t];
+                for (int t = 0; t < R; t++) b0[t * (P + P / 32)] = y[c][t];
+            } else if constexpr (P == 1 && 32 % R == 0) {
+#pragma unroll
+                for (int t = 0; t < R; t++) b0[t] = y[c][t];
+            } else if constexpr (P == 16 && R % 2 == 0) {
+#pragma unroll
+                for (int t = 0; t < R; t++) b0[16 * t + (t >> 1)] = y[c][t];
+            } else {
+#pragma unroll
+                for (int t = 0; t < R; t++) buf[rix(j + t * P)] = y[c][t];
+            }
         }
     }
     __syncthreads();
