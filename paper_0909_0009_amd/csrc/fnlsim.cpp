@@ -265,6 +265,18 @@ int build_precision_tables(sim_ctx *c, const double *filter)
                 FT[((size_t)l * b.Kpad + j) * b.Mpad + i] = (T)filter[((size_t)l * N + i) * N + j];
     int rc = upload(c, &b.FT, FT.data(), FT.size());
     if (rc) return rc;
+    {
+        // forward layout: one lane's 8 K-steps of a 32-column chunk contiguous
+        std::vector<T> FQ((size_t)(L + 1) * b.nchq * b.Mpad * 32, T(0));
+        for (int l = 0; l <= L; l++)
+            for (int i = 0; i < N; i++)
+                for (int j = 0; j < N; j++) {
+                    const int cq = j / 32, k = j % 4, s4 = (j % 32) / 4;
+                    FQ[((((size_t)l * b.nchq + cq) * b.Mpad + i) * 4 + k) * 8 + s4] =
+                        (T)filter[((size_t)l * N + i) * N + j];
+                }
+        if ((rc = upload(c, &b.FQ, FQ.data(), FQ.size()))) return rc;
+    }
     // twiddles e^{-2 pi i q / n}
     using C2 = typename C2of<T>::type;
     std::vector<C2> tw(sh.nphi);
@@ -470,6 +482,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     b.nk4 = (int)k4.size();
     b.Kpad = (N + 3) / 4 * 4;
     b.Mpad = (N + 63) / 64 * 64;
+    b.nchq = (N + 31) / 32;
 
     // ---- device
     int rc;

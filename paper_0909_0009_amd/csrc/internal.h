@@ -76,7 +76,10 @@ __host__ __device__ inline long long lm_index(int l, int m) {
 // Device buffers owned by a context.  Element type of phi/G/F/FT/tw is
 // double for the FP64 path and float for the FP32 path (void* here).
 struct Bufs {
-    void *FT;          // [L+1][Kpad][Mpad] filter, transposed and zero padded
+    void *FT;          // [L+1][Kpad][Mpad] filter, transposed and zero padded (reverse pass)
+    void *FQ;          // [L+1][nchq][Mpad][4][8] forward filter: FQ(l, c, i, k, s) =
+                       // F_l[i][32 c + 4 s + k], zero padded (one lane's 8 K-steps of
+                       // a 32-column chunk are contiguous)
     double *V;         // [2][L+1][N] V^X_l = W^X_l F_l (linear radial sum)
     double *W;         // [2][L+1][Cpad/2] W^X_ls, zero for padded shells
     double *x;         // [npair] cos theta of the north ring of each pair
@@ -97,8 +100,8 @@ struct Bufs {
     void *tw;          // [nphi] e^{-2 pi i q / nphi}
     double *mu;        // [Cpad/2] sqrt(4 pi) * ensemble <Phi_L^2>(r_s)
     void *phi;         // [nlm rows][Cpad] Phi_L (m-major)
-    void *G;           // [npair][L+1][2][Cpad] synthesis output (E, O)
-    void *F;           // [L+1][npair][2][Cpad] weighted ring spectra (E, O)
+    void *G;           // [npair][L+1][Cpad][2] synthesis output, (E, O) interleaved
+    void *F;           // [L+1][npair][Cpad][2] weighted ring spectra, (E, O) interleaved
     double2 *part;     // [nct][2][nlm] per-column-tile radial sums of Phi_NL
     double2 *aL;       // [2][nlm] linear radial sums
     void *scratch;     // debug / backward staging, [nlm rows][Cpad] elements
@@ -106,7 +109,7 @@ struct Bufs {
     double *fpart;     // reverse pass: [npair * N] per-block dLoss/df_NL shares (lazy)
     double *fbar;      // reverse pass: [fbar_cap] dLoss/df_NL per realization (lazy)
     int fbar_cap;
-    int Kpad, Mpad;
+    int Kpad, Mpad, nchq;
     int nk1, nk2, nk4;
     long long nseedrow;
 };

@@ -103,12 +103,12 @@ constexpr int kFiltLD = 80;  // LDS row stride (elements): conflict-free B reads
 template <typename T> constexpr int filter_blocks() { return sizeof(T) == 4 ? 2 : 1; }
 
 template <typename T>
-__device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FT_in, int Kpad,
-                                            int Mpad, const int2 *__restrict__ tiles_in,
+__device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FQ_in, int Kpad,
+                                            int Mpad, int nchq, const int2 *__restrict__ tiles_in,
                                             const T *__restrict__ noise_in, T *__restrict__ phi_in,
                                             int bx)
 {
-    auto *__restrict__ FT = glb(FT_in);
+    auto *__restrict__ FQ = glb(FQ_in);
     auto *__restrict__ tiles = glb(tiles_in);
     auto *__restrict__ noise = glb(noise_in);
     auto *__restrict__ phi = glb(phi_in);
@@ -122,7 +122,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
     const int N = sh.N, ncol = 2 * (l + 1);
     const long long nlm = sh.nlm;
     const long long base = 2 * lm_index(l, 0);
-    const auto FTl = FT + (long long)l * Kpad * Mpad;
+    const auto FQl = FQ + (long long)l * nchq * Mpad * 32;
     const int RT = (N + 31) / 32, npairs = (RT + 1) / 2;
     // staging role: thread t loads chunk row t / 8, columns 8 (t % 8) .. + 8
     const int sj = threadIdx.x >> 3, sc = (threadIdx.x & 7) * 8;
@@ -161,15 +161,29 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
                 for (int c = 0; c < 4; c++) acc[a][h][c] = typename M::acc{};
         // F^T fragments of a chunk: [tile][half][K-step]
         T af[1][2][2][8];
+        // a lane's 8 K-steps of a chunk for one 16-row half: 8 contiguous values
         auto load_a = [&](int c, T (&A)[2][2][8]) {
+            const auto Fc = FQl + (long long)c * Mpad * 32;
 #pragma unroll
-            for (int ks = 0; ks < 8; ks++) {
-                const int j = 32 * c + 4 * ks + k4;
-                const bool jv = j < Kpad;
+            for (int a = 0; a < 2; a++) {
+                const int t = a == 0 ? tA : tB;
+                const bool has = a == 0 ? hasA : hasB;
 #pragma unroll
                 for (int h = 0; h < 2; h++) {
-                    A[0][h][ks] = (hasA && jv) ? FTl[(long long)j * Mpad + 32 * tA + 16 * h + i16] : T(0);
-                    A[1][h][ks] = (hasB && jv) ? FTl[(long long)j * Mpad + 32 * tB + 16 * h + i16] : T(0);
+                    if (has) {
+                        const auto src = Fc + ((32 * t + 16 * h + i16) * 4 + k4) * 8;
+                        using V4 = typename VecOf<typename std::conditional<sizeof(T) == 4, float4, double4>::type>::t;
+                        const V4 lo = *reinterpret_cast<const GLB V4 *>(src);
+                        const V4 hi = *reinterpret_cast<const GLB V4 *>(src + 4);
+#pragma unroll
+                        for (int q = 0; q < 4; q++) {
+                            A[a][h][q] = lo[q];
+                            A[a][h][4 + q] = hi[q];
+                        }
+                    } else {
+#pragma unroll
+                        for (int ks = 0; ks < 8; ks++) A[a][h][ks] = T(0);
+                    }
                 }
             }
         };
@@ -235,11 +249,11 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, filter_blocks<T>()) void k_filter(Shape sh, const T *__restrict__ FT, int Kpad,
-                                                int Mpad, const int2 *__restrict__ tiles,
+__global__ __launch_bounds__(256, filter_blocks<T>()) void k_filter(Shape sh, const T *__restrict__ FQ, int Kpad,
+                                                int Mpad, int nchq, const int2 *__restrict__ tiles,
                                                 const T *__restrict__ noise, T *__restrict__ phi)
 {
-    body_filter<T>(sh, FT, Kpad, Mpad, tiles, noise, phi, blockIdx.x);
+    body_filter<T>(sh, FQ, Kpad, Mpad, nchq, tiles, noise, phi, blockIdx.x);
 }
 
 // ------------------------------------------------------- linear radial sum
@@ -269,14 +283,33 @@ __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *_
     double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
     const auto VT = V + (long long)l * sh.N;
     const auto VE = V + (long long)(sh.L + 1) * sh.N + (long long)l * sh.N;
-    for (int j = 0; j < sh.N; j++) {
-        const auto nz = noise + 2 * ((long long)j * sh.nlm + idx);
-        const double re = (double)nz[0];
-        const double im = m0 ? 0.0 : (double)nz[1];
-        neumaier(s[0], c[0], VT[j] * re);
-        neumaier(s[1], c[1], VT[j] * im);
-        neumaier(s[2], c[2], VE[j] * re);
-        neumaier(s[3], c[3], VE[j] * im);
+    // 8 shells per step: their loads are all issued before the (sequential)
+    // compensated sums, so each wave keeps 8 rows of the noise in flight
+    using C2 = typename Mt<T>::c2;
+    constexpr int U = 8;
+    const auto nz0 = noise + 2 * idx;
+    const long long rstride = 2 * sh.nlm;
+    for (int j0 = 0; j0 < sh.N; j0 += U) {
+        C2 v[U];
+        double vt[U], ve[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int j = min(j0 + u, sh.N - 1);
+            v[u] = gload(reinterpret_cast<const GLB C2 *>(nz0 + (long long)j * rstride));
+            vt[u] = VT[j];
+            ve[u] = VE[j];
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            if (j0 + u < sh.N) {
+                const double re = (double)v[u].x;
+                const double im = m0 ? 0.0 : (double)v[u].y;
+                neumaier(s[0], c[0], vt[u] * re);
+                neumaier(s[1], c[1], vt[u] * im);
+                neumaier(s[2], c[2], ve[u] * re);
+                neumaier(s[3], c[3], ve[u] * im);
+            }
+        }
     }
     gstore(aL + idx, make_double2(s[0] + c[0], s[1] + c[1]));
     gstore(aL + sh.nlm + idx, make_double2(s[2] + c[2], s[3] + c[3]));
@@ -1359,8 +1392,8 @@ __global__ __launch_bounds__(256, filter_blocks<T>()) void g_filter(const GroupI
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
     if (lb >= g.b.nk1) return;
-    body_filter<T>(g.sh, (const T *)g.b.FT, g.b.Kpad, g.b.Mpad, g.b.k1tiles, (const T *)g.noise,
-                   (T *)g.b.phi, lb);
+    body_filter<T>(g.sh, (const T *)g.b.FQ, g.b.Kpad, g.b.Mpad, g.b.nchq, g.b.k1tiles,
+                   (const T *)g.noise, (T *)g.b.phi, lb);
 }
 
 template <typename T, int CF>
@@ -1770,11 +1803,12 @@ hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void
 {
     dim3 grid(b.nk1);
     if (sh.fp32)
-        hipLaunchKernelGGL(k_filter<float>, grid, dim3(256), 0, s, sh, (const float *)b.FT, b.Kpad,
-                           b.Mpad, b.k1tiles, (const float *)noise, (float *)phi_out);
+        hipLaunchKernelGGL(k_filter<float>, grid, dim3(256), 0, s, sh, (const float *)b.FQ, b.Kpad,
+                           b.Mpad, b.nchq, b.k1tiles, (const float *)noise, (float *)phi_out);
     else
-        hipLaunchKernelGGL(k_filter<double>, grid, dim3(256), 0, s, sh, (const double *)b.FT,
-                           b.Kpad, b.Mpad, b.k1tiles, (const double *)noise, (double *)phi_out);
+        hipLaunchKernelGGL(k_filter<double>, grid, dim3(256), 0, s, sh, (const double *)b.FQ,
+                           b.Kpad, b.Mpad, b.nchq, b.k1tiles, (const double *)noise,
+                           (double *)phi_out);
     return hipGetLastError();
 }
 
