@@ -98,9 +98,9 @@ __device__ inline int l_of_index(long long idx) {
 // the four waves; the F^T fragments of the next chunk load while the block
 // waits at the chunk's barrier.  The noise is read from HBM once.
 constexpr int kFiltLD = 80;  // LDS row stride (elements): conflict-free B reads
-// blocks per CU the filter's register budget is held to (FP64 holds twice
-// the accumulator registers)
-template <typename T> constexpr int filter_blocks() { return sizeof(T) == 4 ? 2 : 1; }
+// blocks per CU the filter's register budget is held to (two: the FP64
+// kernel spills a few registers there and is still faster than at one)
+template <typename T> constexpr int filter_blocks() { return 2; }
 
 template <typename T>
 __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FQ_in, int Kpad,
