@@ -264,7 +264,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="paper", choices=["paper", "medium", "grad", "tiny"])
-    ap.add_argument("--cpu-shells", type=int, default=2)
+    ap.add_argument("--cpu-shells", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp32-only", action="store_true", help="skip the FP64 path (profiling runs)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
