@@ -26,6 +26,7 @@
  * thread count.
  */
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -572,4 +573,69 @@ int orc_adjoint(const orc_problem *P, const double *noise, double fnl,
     free(x);
     free(wq);
     return 0;
+}
+
+
+/* ------------------------------------------------------ counter-based noise */
+
+/* One Philox round: two 32x32 -> 64-bit products, words permuted and mixed
+ * with the key (Salmon et al., SC'11, Sect. 4 and Table 1: multipliers
+ * 0xD2511F53, 0xCD9E8D57; key increments 0x9E3779B9, 0xBB67AE85). */
+void orc_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2],
+                       unsigned int out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; r++) {
+        if (r > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0;
+        c1 = n1;
+        c2 = n2;
+        c3 = n3;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+void orc_noise(int lmax, int nshell, unsigned long long seed, double *noise)
+{
+    const long long nlm = (long long)(lmax + 1) * (lmax + 2) / 2;
+    const unsigned int key[2] = {(unsigned int)(seed & 0xffffffffu), (unsigned int)(seed >> 32)};
+    const double two_m53 = 1.0 / 9007199254740992.0; /* 2^-53 */
+    const double pi = 3.14159265358979323846;
+    for (int j = 0; j < nshell; j++)
+        for (int l = 0; l <= lmax; l++)
+            for (int m = 0; m <= l; m++) {
+                const long long idx = (long long)l * (l + 1) / 2 + m;
+                const unsigned int ctr[4] = {(unsigned int)(idx & 0xffffffffu),
+                                             (unsigned int)((unsigned long long)idx >> 32),
+                                             (unsigned int)j, 0x6e6f6973u};
+                unsigned int x[4];
+                orc_philox4x32_10(ctr, key, x);
+                const uint64_t a = (((uint64_t)x[1] << 32) | x[0]) >> 11;
+                const uint64_t b = (((uint64_t)x[3] << 32) | x[2]) >> 11;
+                const double u1 = (double)(a + 1) * two_m53;
+                const double u2 = (double)b * two_m53;
+                const double rad = sqrt(-2.0 * log(u1));
+                const double g0 = rad * cos(2.0 * pi * u2);
+                const double g1 = rad * sin(2.0 * pi * u2);
+                double *o = noise + 2 * ((size_t)j * nlm + idx);
+                if (m == 0) {
+                    o[0] = g0;
+                    o[1] = 0.0;
+                } else {
+                    o[0] = g0 / sqrt(2.0);
+                    o[1] = g1 / sqrt(2.0);
+                }
+            }
 }

@@ -78,6 +78,21 @@ int orc_adjoint(const orc_problem *P, const double *noise, double fnl,
                 const double *gT, const double *gE,
                 double *grad_n, double *grad_fnl);
 
+/* Counter-based noise (regenerated from a seed instead of stored; the
+ * paper's memory remark in Sect. 3).  Philox4x32 with 10 rounds (Salmon,
+ * Moraes, Dror and Shaw, SC'11): counter (c0..c3), key (k0, k1) -> 4 words. */
+void orc_philox4x32_10(const unsigned int ctr[4], const unsigned int key[2],
+                       unsigned int out[4]);
+
+/* noise[N][n_lm] complex for one realization seed: for shell j and index
+ * idx = l(l+1)/2 + m, Philox of counter (idx mod 2^32, idx / 2^32, j,
+ * 0x6e6f6973) under key (seed mod 2^32, seed / 2^32) gives words x0..x3;
+ * U1 = (((x1 << 32 | x0) >> 11) + 1) 2^-53 in (0, 1],
+ * U2 = ((x3 << 32 | x2) >> 11) 2^-53 in [0, 1); Box-Muller
+ * g0 = sqrt(-2 ln U1) cos(2 pi U2), g1 = sqrt(-2 ln U1) sin(2 pi U2);
+ * n = (g0, g1) / sqrt(2) for m > 0 and (g0, 0) for m = 0 (E|n|^2 = 1).       */
+void orc_noise(int lmax, int nshell, unsigned long long seed, double *noise);
+
 #ifdef __cplusplus
 }
 #endif

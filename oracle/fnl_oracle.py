@@ -43,6 +43,10 @@ def lib():
         _lib.orc_forward.argtypes = [ctypes.POINTER(_Problem), vp, dp] + [vp] * 9
         _lib.orc_forward.restype = ip
         _lib.orc_adjoint.argtypes = [ctypes.POINTER(_Problem), vp, dp, vp, vp, vp, vp]
+        _lib.orc_philox4x32_10.argtypes = [vp, vp, vp]
+        _lib.orc_philox4x32_10.restype = None
+        _lib.orc_noise.argtypes = [ip, ip, ctypes.c_ulonglong, vp]
+        _lib.orc_noise.restype = None
         _lib.orc_adjoint.restype = ip
     return _lib
 
@@ -180,3 +184,20 @@ def radial_weights(problem):
 
 
 SQRT4PI = math.sqrt(4.0 * math.pi)
+
+
+def philox4x32_10(ctr, key):
+    """Philox4x32-10 of a 4-word counter under a 2-word key -> 4 words."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c.ctypes.data, k.ctypes.data, out.ctypes.data)
+    return out
+
+
+def seeded_noise(L, N, seed):
+    """Counter-based noise [N][n_lm] complex128 of one realization seed
+    (definition in fnl_oracle.h, orc_noise)."""
+    out = np.empty((N, nlm(L)), dtype=np.complex128)
+    lib().orc_noise(int(L), int(N), int(seed), out.ctypes.data)
+    return out
