@@ -130,6 +130,32 @@ def time_path(torch, fnlsim, p, cfg, noise_np, precision, steps, warmup):
     return res
 
 
+def time_seeded(torch, sim, cfg, steps, warmup):
+    """The same forward with counter-based noise generated inside the linear
+    radial sum and the filter (sim_forward_seeded): no noise buffer is read.
+    A new seed per step."""
+    stream = torch.cuda.current_stream()
+    for k in range(warmup):
+        sim.forward_seeded([1000 + k], cfg["fnl"])
+    torch.cuda.synchronize()
+    sim.profile(True)
+    sim.profile_read()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for k in range(steps):
+        sim.forward_seeded([2000 + k], cfg["fnl"])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st = sim.profile_read()
+    sim.profile(False)
+    elem = 8 if sim.precision == "fp32" else 16
+    return {"value": round(1000.0 / ms, 4), "unit": "maps/s", "ms_per_step": round(ms, 4),
+            "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items()},
+            "noise_bytes_not_stored": elem * sim.nshell * sim.n_lm}
+
+
 def time_fwd_bwd(torch, fnlsim, inputs, precision, steps, warmup):
     """Forward + hand-written reverse pass per step at the differentiation
     workload (lmax 512, 96 nodes, 769 x 1536 grid), one realization."""
@@ -270,6 +296,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd leg (lmax 512)")
+    ap.add_argument("--no-seeded", action="store_true",
+                    help="skip the counter-based-noise forward leg")
     ap.add_argument("--batch", action="store_true",
                     help="also time the uneven 32-realization batch against sequential calls")
     args = ap.parse_args()
@@ -307,6 +335,10 @@ def main():
     log(f"fp32: {r32['ms']:.3f} ms/step")
     dom, roof = roofline(r32["sim"], r32["stages"], "fp32", args.steps)
     stages32 = {k: round(v[0] / max(v[1], 1), 4) for k, v in r32["stages"].items()}
+    seeded = None
+    if not args.no_seeded:
+        seeded = {"fp32": time_seeded(torch, r32["sim"], cfg, args.steps, args.warmup)}
+        log(f"seeded fp32: {seeded['fp32']['ms_per_step']:.3f} ms/step")
     r32["sim"].close()
     torch.cuda.empty_cache()
     fp64 = None
@@ -315,6 +347,9 @@ def main():
         r64 = time_path(torch, fnlsim, p, cfg, noise_np, "fp64", args.steps, args.warmup)
         log(f"fp64: {r64['ms']:.3f} ms/step")
         dom64, roof64 = roofline(r64["sim"], r64["stages"], "fp64", args.steps)
+        if seeded is not None:
+            seeded["fp64"] = time_seeded(torch, r64["sim"], cfg, args.steps, args.warmup)
+            log(f"seeded fp64: {seeded['fp64']['ms_per_step']:.3f} ms/step")
         fp64 = {"value": round(1000.0 / r64["ms"], 4), "ms_per_step": round(r64["ms"], 4),
                 "shells_per_s": round(1000.0 / r64["ms"] * N, 2),
                 "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r64["stages"].items()},
@@ -366,6 +401,7 @@ def main():
         "roofline": roof,
         "fp64": fp64,
         "mixed_vs_fp64_max_rel_err": err,
+        "seeded": seeded,
         "fwd_bwd": grad,
         "batch": batch,
         "cpu_baseline": cpu,

@@ -129,6 +129,30 @@ int sim_init(sim_ctx **out, int lmax, int nshell,
 int sim_forward(sim_ctx *ctx, const void *noise, int R, const double *fnl,
                 void *aT, void *aE, void *aT_nl, void *aE_nl);
 
+/* Counter-based noise (the memory remark of Sect. 3: the white noise of a
+ * realization is a function of its seed, so it need not be stored).
+ * Value (l, m, j) of realization `seed`: Philox4x32-10 (Salmon et al., SC'11)
+ * of counter (idx mod 2^32, idx / 2^32, j, 0x6e6f6973), idx = l(l+1)/2 + m,
+ * under key (seed mod 2^32, seed / 2^32) gives x0..x3;
+ * u1 = (((x1 2^32 + x0) >> 11) + 1) 2^-53 in (0, 1],
+ * u2 = ((x3 2^32 + x2) >> 11) 2^-53 in [0, 1);
+ * g0 + i g1 = sqrt(-2 ln u1) e^{2 pi i u2} (Box-Muller, in FP64);
+ * n = (g0 + i g1)/sqrt(2) for m > 0 and g0 for m = 0, then rounded to the
+ * precision's noise dtype.
+ *
+ * sim_noise writes that noise for seeds[0..R) into device
+ * noise [R][N][n_lm] complex (the layout and dtype sim_forward reads).
+ * sim_forward_seeded is sim_forward on that noise, with the noise generated
+ * inside the kernels that read it (no noise buffer, no noise traffic): its
+ * outputs equal sim_forward(sim_noise(seeds)) bit for bit.
+ *   seeds    host [R] 64-bit realization seeds
+ *   others   as for sim_forward
+ * Asynchronous on the context stream.  SIM_EINVAL for R < 1 or a null
+ * required pointer (nothing launched). */
+int sim_noise(sim_ctx *ctx, const unsigned long long *seeds, int R, void *noise);
+int sim_forward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, const double *fnl,
+                       void *aT, void *aE, void *aT_nl, void *aE_nl);
+
 /* Reverse-mode derivative of sim_forward for a real loss.
  *   gT, gE    device [R][n_lm] complex128 cotangents dLoss/dRe a + i dLoss/dIm a
  *   grad_n    device [R][N][n_lm] complex, dtype of the noise, same convention

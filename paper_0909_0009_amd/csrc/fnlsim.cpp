@@ -301,7 +301,7 @@ int build_precision_tables(sim_ctx *c, const double *filter)
 }
 
 int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
-                double2 *aTn, double2 *aEn);
+                double2 *aTn, double2 *aEn, unsigned long long seed = 0);
 
 // Build a context; force_cf = 0 picks the column tile by the padding rule.
 int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double *w,
@@ -679,14 +679,16 @@ static int prof_mark(sim_ctx *c, int stage)
     } while (0)
 
 namespace {
+// noise == nullptr: the noise of realization `seed` is generated inside the
+// linear radial sum and the filter instead of read.
 int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
-                double2 *aTn, double2 *aEn)
+                double2 *aTn, double2 *aEn, unsigned long long seed)
 {
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
     hipStream_t s = c->stream;
-    STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s));
-    STAGE(c, 1, fnl::launch_filter(sh, b, noise, b.phi, s));
+    STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s, seed));
+    STAGE(c, 1, fnl::launch_filter(sh, b, noise, b.phi, s, seed));
     STAGE(c, 2, fnl::launch_synth(sh, b, b.phi, b.G, s));
     STAGE(c, 3, fnl::launch_ring(sh, b, b.G, b.F, nullptr, 0, s));
     STAGE(c, 4, fnl::launch_anal(sh, b, b.F, nullptr, 0, s));
@@ -748,6 +750,38 @@ int sim_forward(sim_ctx *c, const void *noise, int R, const double *fnl, void *a
         const int rc = forward_one(c, nz, fnl[r], t, e, tn, en);
         if (rc) return rc;
     }
+    return SIM_OK;
+}
+
+int sim_forward_seeded(sim_ctx *c, const unsigned long long *seeds, int R, const double *fnl,
+                       void *aT, void *aE, void *aT_nl, void *aE_nl)
+{
+    if (!c) return SIM_EINVAL;
+    if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    if (!seeds || !fnl || !aT || !aE) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    for (int r = 0; r < R; r++)
+        if (!std::isfinite(fnl[r])) return fail(c, SIM_EINVAL, "fnl[%d] is not finite", r);
+    const Shape &sh = c->sh;
+    for (int r = 0; r < R; r++) {
+        double2 *t = (double2 *)aT + sh.nlm * r;
+        double2 *e = (double2 *)aE + sh.nlm * r;
+        double2 *tn = aT_nl ? (double2 *)aT_nl + sh.nlm * r : nullptr;
+        double2 *en = aE_nl ? (double2 *)aE_nl + sh.nlm * r : nullptr;
+        const int rc = forward_one(c, nullptr, fnl[r], t, e, tn, en, seeds[r]);
+        if (rc) return rc;
+    }
+    return SIM_OK;
+}
+
+int sim_noise(sim_ctx *c, const unsigned long long *seeds, int R, void *noise)
+{
+    if (!c) return SIM_EINVAL;
+    if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    if (!seeds || !noise) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    const Shape &sh = c->sh;
+    const size_t nbytes = (sh.fp32 ? 8 : 16) * (size_t)sh.N * sh.nlm;
+    for (int r = 0; r < R; r++)
+        HIPCHECK(c, fnl::launch_noise(sh, seeds[r], (char *)noise + nbytes * r, c->stream));
     return SIM_OK;
 }
 

@@ -140,9 +140,14 @@ hipError_t prepare_group_ring(int fp32, int nphi, int planned);
 
 // ----- launchers (kernels.hip); all asynchronous on `s`.
 hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);  // seeds, lstart, cmin
-hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);
+// noise == nullptr: the noise of realization `seed` is generated in the
+// kernel (counter-based, as launch_noise writes it) instead of read.
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s,
+                             unsigned long long seed = 0);
 hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
-                         hipStream_t s);
+                         hipStream_t s, unsigned long long seed = 0);
+// noise of realization `seed`, [N][nlm] complex in the path's precision
+hipError_t launch_noise(const Shape &sh, unsigned long long seed, void *out, hipStream_t s);
 hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
                         hipStream_t s);
 // mode 0: square minus mean and forward transform into F; 1: write maps.

@@ -86,6 +86,63 @@ __device__ inline int l_of_index(long long idx) {
     return l;
 }
 
+// ----------------------------------------------------- counter-based noise
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror and Shaw, SC'11): each round
+// multiplies words 0 and 2 by fixed odd constants, swaps the halves of the
+// 64-bit products into the other two words and mixes in the round key; the key
+// advances by two Weyl increments between rounds.  Stateless: the output is a
+// function of (counter, key) only.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, unsigned k0, unsigned k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        // one 32x32 -> 64-bit multiply per product (v_mad_u64_u32)
+        const unsigned long long p0 = (unsigned long long)c.x * 0xD2511F53u;
+        const unsigned long long p1 = (unsigned long long)c.z * 0xCD9E8D57u;
+        c = make_uint4((unsigned)(p1 >> 32) ^ c.y ^ k0, (unsigned)p1,
+                       (unsigned)(p0 >> 32) ^ c.w ^ k1, (unsigned)p0);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// Noise value n_lm(r_j) of one realization seed (index idx = l(l+1)/2 + m):
+// Philox of counter (idx, j, tag) under the seed as key, two 53-bit uniforms,
+// Box-Muller; (g0, g1)/sqrt(2) for m > 0 and (g0, 0) for m = 0, so that
+// E|n|^2 = 1 (a complex unit Gaussian, real for m = 0).
+__device__ __forceinline__ double2 seeded_noise(unsigned long long seed, long long idx, int j,
+                                                bool m0)
+{
+    const uint4 x = philox4x32_10(make_uint4((unsigned)idx, (unsigned)((unsigned long long)idx >> 32),
+                                             (unsigned)j, 0x6e6f6973u),
+                                  (unsigned)seed, (unsigned)(seed >> 32));
+    const unsigned long long a = (((unsigned long long)x.y << 32) | x.x) >> 11;
+    const unsigned long long b = (((unsigned long long)x.w << 32) | x.z) >> 11;
+    const double u1 = (double)(a + 1) * 0x1.0p-53;  // (0, 1]
+    const double u2 = (double)b * 0x1.0p-53;        // [0, 1)
+    const double rad = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(6.283185307179586477 * u2, &sn, &cs);
+    if (m0) return make_double2(rad * cs, 0.0);
+    const double h = 0.70710678118654752440;  // 1/sqrt(2)
+    return make_double2(rad * cs * h, rad * sn * h);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_noise(Shape sh, unsigned long long seed, T *__restrict__ out)
+{
+    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (long long)sh.N * sh.nlm) return;
+    const int j = (int)(t / sh.nlm);
+    const long long idx = t - (long long)j * sh.nlm;
+    const int l = l_of_index(idx);
+    const double2 g = seeded_noise(seed, idx, j, lm_index(l, 0) == idx);
+    out[2 * t] = (T)g.x;
+    out[2 * t + 1] = (T)g.y;
+}
+
 // ---------------------------------------------------------------- filter
 
 // Block = (l, 64-column tile), every output row.  Columns are c = 2m +
@@ -99,14 +156,20 @@ __device__ inline int l_of_index(long long idx) {
 // waits at the chunk's barrier.  The noise is read from HBM once.
 constexpr int kFiltLD = 80;  // LDS row stride (elements): conflict-free B reads
 // blocks per CU the filter's register budget is held to (two: the FP64
-// kernel spills a few registers there and is still faster than at one)
-template <typename T> constexpr int filter_blocks() { return 2; }
+// kernel spills a few registers there and is still faster than at one; the
+// FP64 kernel that generates its noise needs the whole register file)
+template <typename T, bool SEEDED> constexpr int filter_blocks()
+{
+    return SEEDED && sizeof(T) == 8 ? 1 : 2;
+}
 
-template <typename T>
+// SEEDED: the noise is generated from `seed` (seeded_noise) instead of read
+// from noise_in.
+template <typename T, bool SEEDED = false>
 __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FQ_in, int Kpad,
                                             int Mpad, int nchq, const int2 *__restrict__ tiles_in,
                                             const T *__restrict__ noise_in, T *__restrict__ phi_in,
-                                            int bx)
+                                            unsigned long long seed, int bx)
 {
     auto *__restrict__ FQ = glb(FQ_in);
     auto *__restrict__ tiles = glb(tiles_in);
@@ -134,8 +197,15 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
             C2 w;
             w.x = T(0);
             w.y = T(0);
-            if (j < N && col < ncol)
-                w = gload(reinterpret_cast<const GLB C2 *>(noise + (long long)j * 2 * nlm + base + col));
+            if (j < N && col < ncol) {
+                if constexpr (!SEEDED) {
+                    w = gload(reinterpret_cast<const GLB C2 *>(noise + (long long)j * 2 * nlm + base + col));
+                } else {
+                    const double2 g = seeded_noise(seed, base / 2 + col / 2, j, col == 0);
+                    w.x = (T)g.x;
+                    w.y = (T)g.y;
+                }
+            }
             v[e] = w.x;
             v[e + 1] = col == 0 ? T(0) : w.y;  // Im of m = 0 is ignored
         }
@@ -248,12 +318,13 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256, filter_blocks<T>()) void k_filter(Shape sh, const T *__restrict__ FQ, int Kpad,
+template <typename T, bool SEEDED>
+__global__ __launch_bounds__(256, (filter_blocks<T, SEEDED>())) void k_filter(Shape sh, const T *__restrict__ FQ, int Kpad,
                                                 int Mpad, int nchq, const int2 *__restrict__ tiles,
-                                                const T *__restrict__ noise, T *__restrict__ phi)
+                                                const T *__restrict__ noise, T *__restrict__ phi,
+                                                unsigned long long seed)
 {
-    body_filter<T>(sh, FQ, Kpad, Mpad, nchq, tiles, noise, phi, blockIdx.x);
+    body_filter<T, SEEDED>(sh, FQ, Kpad, Mpad, nchq, tiles, noise, phi, seed, blockIdx.x);
 }
 
 // ------------------------------------------------------- linear radial sum
@@ -268,10 +339,11 @@ __device__ inline void neumaier(double &s, double &c, double v)
     s = t;
 }
 
-template <typename T>
+template <typename T, bool SEEDED = false>
 __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *__restrict__ V_in,
                                                 const T *__restrict__ noise_in,
-                                                double2 *__restrict__ aL_in, int bid)
+                                                double2 *__restrict__ aL_in,
+                                                unsigned long long seed, int bid)
 {
     auto *__restrict__ V = glb(V_in);
     auto *__restrict__ noise = glb(noise_in);
@@ -295,7 +367,13 @@ __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *_
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int j = min(j0 + u, sh.N - 1);
-            v[u] = gload(reinterpret_cast<const GLB C2 *>(nz0 + (long long)j * rstride));
+            if constexpr (!SEEDED) {
+                v[u] = gload(reinterpret_cast<const GLB C2 *>(nz0 + (long long)j * rstride));
+            } else {  // generated from the seed; rounded as a stored noise value would be
+                const double2 g = seeded_noise(seed, idx, j, m0);
+                v[u].x = (T)g.x;
+                v[u].y = (T)g.y;
+            }
             vt[u] = VT[j];
             ve[u] = VE[j];
         }
@@ -315,12 +393,12 @@ __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *_
     gstore(aL + sh.nlm + idx, make_double2(s[2] + c[2], s[3] + c[3]));
 }
 
-template <typename T>
+template <typename T, bool SEEDED>
 __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__restrict__ V,
                                                     const T *__restrict__ noise,
-                                                    double2 *__restrict__ aL)
+                                                    double2 *__restrict__ aL, unsigned long long seed)
 {
-    body_radial_lin<T>(sh, V, noise, aL, blockIdx.x);
+    body_radial_lin<T, SEEDED>(sh, V, noise, aL, seed, blockIdx.x);
 }
 
 // -------------------------------------------------------- Legendre synthesis
@@ -1380,11 +1458,11 @@ __global__ __launch_bounds__(256) void g_radial_lin(const GroupItem *__restrict_
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
     if (lb >= (int)((g.sh.nlm + 255) / 256)) return;
-    body_radial_lin<T>(g.sh, g.b.V, (const T *)g.noise, g.b.aL, lb);
+    body_radial_lin<T>(g.sh, g.b.V, (const T *)g.noise, g.b.aL, 0ull, lb);
 }
 
 template <typename T>
-__global__ __launch_bounds__(256, filter_blocks<T>()) void g_filter(const GroupItem *__restrict__ it,
+__global__ __launch_bounds__(256, (filter_blocks<T, false>())) void g_filter(const GroupItem *__restrict__ it,
                                                 const int *__restrict__ ord,
                                                 const int *__restrict__ off, int n)
 {
@@ -1393,7 +1471,7 @@ __global__ __launch_bounds__(256, filter_blocks<T>()) void g_filter(const GroupI
     const GroupItem &g = it[ord[k]];
     if (lb >= g.b.nk1) return;
     body_filter<T>(g.sh, (const T *)g.b.FQ, g.b.Kpad, g.b.Mpad, g.b.nchq, g.b.k1tiles,
-                   (const T *)g.noise, (T *)g.b.phi, lb);
+                   (const T *)g.noise, (T *)g.b.phi, 0ull, lb);
 }
 
 template <typename T, int CF>
@@ -1798,29 +1876,63 @@ hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
-                         hipStream_t s)
+template <bool SEEDED>
+static void filter_launch(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
+                          hipStream_t s, unsigned long long seed)
 {
     dim3 grid(b.nk1);
     if (sh.fp32)
-        hipLaunchKernelGGL(k_filter<float>, grid, dim3(256), 0, s, sh, (const float *)b.FQ, b.Kpad,
-                           b.Mpad, b.nchq, b.k1tiles, (const float *)noise, (float *)phi_out);
+        hipLaunchKernelGGL((k_filter<float, SEEDED>), grid, dim3(256), 0, s, sh,
+                           (const float *)b.FQ, b.Kpad, b.Mpad, b.nchq, b.k1tiles,
+                           (const float *)noise, (float *)phi_out, seed);
     else
-        hipLaunchKernelGGL(k_filter<double>, grid, dim3(256), 0, s, sh, (const double *)b.FQ,
-                           b.Kpad, b.Mpad, b.nchq, b.k1tiles, (const double *)noise,
-                           (double *)phi_out);
+        hipLaunchKernelGGL((k_filter<double, SEEDED>), grid, dim3(256), 0, s, sh,
+                           (const double *)b.FQ, b.Kpad, b.Mpad, b.nchq, b.k1tiles,
+                           (const double *)noise, (double *)phi_out, seed);
+}
+
+hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
+                         hipStream_t s, unsigned long long seed)
+{
+    if (noise)
+        filter_launch<false>(sh, b, noise, phi_out, s, 0);
+    else
+        filter_launch<true>(sh, b, nullptr, phi_out, s, seed);
     return hipGetLastError();
 }
 
-hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s)
+template <bool SEEDED>
+static void radial_lin_launch(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s,
+                              unsigned long long seed)
 {
     dim3 grid(blocks_for(sh.nlm, 256));
     if (sh.fp32)
-        hipLaunchKernelGGL(k_radial_lin<float>, grid, dim3(256), 0, s, sh, b.V,
-                           (const float *)noise, b.aL);
+        hipLaunchKernelGGL((k_radial_lin<float, SEEDED>), grid, dim3(256), 0, s, sh, b.V,
+                           (const float *)noise, b.aL, seed);
     else
-        hipLaunchKernelGGL(k_radial_lin<double>, grid, dim3(256), 0, s, sh, b.V,
-                           (const double *)noise, b.aL);
+        hipLaunchKernelGGL((k_radial_lin<double, SEEDED>), grid, dim3(256), 0, s, sh, b.V,
+                           (const double *)noise, b.aL, seed);
+}
+
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s,
+                             unsigned long long seed)
+{
+    if (noise)
+        radial_lin_launch<false>(sh, b, noise, s, 0);
+    else
+        radial_lin_launch<true>(sh, b, nullptr, s, seed);
+    return hipGetLastError();
+}
+
+hipError_t launch_noise(const Shape &sh, unsigned long long seed, void *out, hipStream_t s)
+{
+    const long long n = (long long)sh.N * sh.nlm;
+    if (n == 0) return hipSuccess;
+    dim3 grid(blocks_for(n, 256));
+    if (sh.fp32)
+        hipLaunchKernelGGL(k_noise<float>, grid, dim3(256), 0, s, sh, seed, (float *)out);
+    else
+        hipLaunchKernelGGL(k_noise<double>, grid, dim3(256), 0, s, sh, seed, (double *)out);
     return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ SIM_STAGE_FILTER, SIM_STAGE_NONLIN, SIM_STAGE_MAPS = 1, 2, 3
 SIM_NSTAGE = 6
 STAGE_NAMES = ("radial_lin", "filter", "synth", "ring", "anal", "combine")
 
-EXPORTS = ("sim_init", "sim_forward", "sim_backward", "sim_debug_stage", "sim_get_info",
+EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_backward",
+           "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
            "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
            "sim_destroy", "sim_last_error")
@@ -66,6 +67,10 @@ def lib():
         L.sim_init.restype = ip
         L.sim_forward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         L.sim_forward.restype = ip
+        L.sim_forward_seeded.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
+        L.sim_forward_seeded.restype = ip
+        L.sim_noise.argtypes = [vp, vp, ip, vp]
+        L.sim_noise.restype = ip
         L.sim_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         L.sim_backward.restype = ip
         L.sim_debug_stage.argtypes = [vp, ip, vp, vp]
@@ -191,6 +196,42 @@ class Simulator:
         rc = lib().sim_forward(self._h, noise.data_ptr(), R, f.ctypes.data, aT.data_ptr(),
                                aE.data_ptr(), aTn.data_ptr() if want_nl else None,
                                aEn.data_ptr() if want_nl else None)
+        _check(rc, self._h)
+        return (aT, aE, aTn, aEn) if want_nl else (aT, aE)
+
+    @staticmethod
+    def _seeds(seeds):
+        if isinstance(seeds, (int, np.integer)):
+            seeds = [seeds]
+        vals = list(seeds)
+        if not vals or any(isinstance(v, bool) or not isinstance(v, (int, np.integer))
+                           for v in vals):
+            raise ValueError("seeds must be one or more integers")
+        if any(int(v) < 0 or int(v) >= 2**64 for v in vals):
+            raise ValueError("seeds must lie in [0, 2^64)")
+        return np.array([int(v) for v in vals], dtype=np.uint64)
+
+    def noise(self, seeds, device="cuda"):
+        """Counter-based noise of each seed: [R][N][n_lm] CUDA tensor of
+        noise_dtype (the generator defined in include/fnlsim.h)."""
+        s = self._seeds(seeds)
+        out = torch.empty((s.size, self.nshell, self.n_lm), dtype=self.noise_dtype, device=device)
+        _check(lib().sim_noise(self._h, s.ctypes.data, s.size, out.data_ptr()), self._h)
+        return out
+
+    def forward_seeded(self, seeds, fnl, want_nl=False, device="cuda"):
+        """forward(noise(seeds), fnl) with the noise generated inside the
+        kernels instead of stored (bitwise the same result)."""
+        s = self._seeds(seeds)
+        R = s.size
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(fnl, dtype=np.float64), (R,)))
+        aT = torch.empty((R, self.n_lm), dtype=torch.complex128, device=device)
+        aE = torch.empty_like(aT)
+        aTn = torch.empty_like(aT) if want_nl else None
+        aEn = torch.empty_like(aT) if want_nl else None
+        rc = lib().sim_forward_seeded(self._h, s.ctypes.data, R, f.ctypes.data, aT.data_ptr(),
+                                      aE.data_ptr(), aTn.data_ptr() if want_nl else None,
+                                      aEn.data_ptr() if want_nl else None)
         _check(rc, self._h)
         return (aT, aE, aTn, aEn) if want_nl else (aT, aE)
 
