@@ -75,7 +75,8 @@ def measured_traffic(stage, precision):
         return None
     T = "float" if precision == "fp32" else "double"
     pat = re.compile(rf"^k_{stage}<{T}[,>]")
-    hits = [v for k, v in rec["kernels"].items() if pat.match(k)]
+    # the stored-noise instantiation (", true>" marks the seeded filter)
+    hits = [v for k, v in rec["kernels"].items() if pat.match(k) and not k.endswith(", true>")]
     return round(hits[0]["traffic_bytes"]) if len(hits) == 1 else None
 
 

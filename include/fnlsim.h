@@ -143,8 +143,10 @@ int sim_forward(sim_ctx *ctx, const void *noise, int R, const double *fnl,
  * sim_noise writes that noise for seeds[0..R) into device
  * noise [R][N][n_lm] complex (the layout and dtype sim_forward reads).
  * sim_forward_seeded is sim_forward on that noise, with the noise generated
- * inside the kernels that read it (no noise buffer, no noise traffic): its
- * outputs equal sim_forward(sim_noise(seeds)) bit for bit.
+ * inside the filter (no noise buffer, no noise traffic), which then also
+ * forms the linear radial sums: aT_nl, aE_nl equal those of
+ * sim_forward(sim_noise(seeds)) bit for bit, aT and aE to FP64 rounding (the
+ * linear radial sum adds the same products in another order).
  *   seeds    host [R] 64-bit realization seeds
  *   others   as for sim_forward
  * Asynchronous on the context stream.  SIM_EINVAL for R < 1 or a null

@@ -680,14 +680,14 @@ static int prof_mark(sim_ctx *c, int stage)
 
 namespace {
 // noise == nullptr: the noise of realization `seed` is generated inside the
-// linear radial sum and the filter instead of read.
+// filter instead of read, and the filter also forms the linear radial sums.
 int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
                 double2 *aTn, double2 *aEn, unsigned long long seed)
 {
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
     hipStream_t s = c->stream;
-    STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s, seed));
+    if (noise) STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s));
     STAGE(c, 1, fnl::launch_filter(sh, b, noise, b.phi, s, seed));
     STAGE(c, 2, fnl::launch_synth(sh, b, b.phi, b.G, s));
     STAGE(c, 3, fnl::launch_ring(sh, b, b.G, b.F, nullptr, 0, s));

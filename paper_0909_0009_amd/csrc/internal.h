@@ -140,10 +140,11 @@ hipError_t prepare_group_ring(int fp32, int nphi, int planned);
 
 // ----- launchers (kernels.hip); all asynchronous on `s`.
 hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);  // seeds, lstart, cmin
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);
 // noise == nullptr: the noise of realization `seed` is generated in the
-// kernel (counter-based, as launch_noise writes it) instead of read.
-hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s,
-                             unsigned long long seed = 0);
+// kernel (counter-based, as launch_noise writes it) instead of read, and the
+// filter also writes the linear radial sums into b.aL (launch_radial_lin's
+// work).
 hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
                          hipStream_t s, unsigned long long seed = 0);
 // noise of realization `seed`, [N][nlm] complex in the path's precision

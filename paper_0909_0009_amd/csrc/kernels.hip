@@ -164,12 +164,15 @@ template <typename T, bool SEEDED> constexpr int filter_blocks()
 }
 
 // SEEDED: the noise is generated from `seed` (seeded_noise) instead of read
-// from noise_in.
+// from noise_in, and the block also forms the linear radial sums of its
+// columns, a^X_L = sum_j V^X_lj n(r_j), into aL (each noise value is then
+// generated once).
 template <typename T, bool SEEDED = false>
 __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FQ_in, int Kpad,
                                             int Mpad, int nchq, const int2 *__restrict__ tiles_in,
                                             const T *__restrict__ noise_in, T *__restrict__ phi_in,
-                                            unsigned long long seed, int bx)
+                                            unsigned long long seed, const double *__restrict__ V_in,
+                                            double2 *__restrict__ aL_in, int bx)
 {
     auto *__restrict__ FQ = glb(FQ_in);
     auto *__restrict__ tiles = glb(tiles_in);
@@ -214,6 +217,25 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
 #pragma unroll
         for (int e = 0; e < 8; e++) nz[buf][sj][sc + e] = v[e];
     };
+    // seeded: per-thread FP64 partial radial sums [X][row group sj][column],
+    // each slot owned by one thread until the final reduction
+    __shared__ double rsum[SEEDED ? 2 : 1][SEEDED ? 32 : 1][SEEDED ? 64 : 1];
+    auto radial_acc = [&](int j0, const T (&v)[8]) {
+        if constexpr (SEEDED) {
+            const int j = min(j0 + sj, N - 1);  // rows past N hold zeros
+            const double vt = glb(V_in)[(long long)l * N + j];
+            const double ve = glb(V_in)[(long long)(sh.L + 1 + l) * N + j];
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                rsum[0][sj][sc + e] += vt * (double)v[e];
+                rsum[1][sj][sc + e] += ve * (double)v[e];
+            }
+        }
+    };
+    if constexpr (SEEDED) {
+#pragma unroll
+        for (int e = 0; e < 8; e++) rsum[0][sj][sc + e] = rsum[1][sj][sc + e] = 0.0;
+    }
 
     for (int q0 = 0; q0 < npairs; q0 += 4) {
         const int q = q0 + wave;
@@ -259,6 +281,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
         };
         T v[8];
         stage_load(0, v);
+        if (q0 == 0) radial_acc(0, v);  // the first round stages every row
         stage_store(0, v);
         load_a(0, af[0]);
         __syncthreads();
@@ -267,7 +290,10 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
             // load; the next chunk's F^T fragments load after the MFMAs
             const int buf = c & 1;
             const bool more = c + 1 < nchunk;
-            if (more) stage_load(32 * (c + 1), v);
+            if (more) {
+                stage_load(32 * (c + 1), v);
+                if (q0 == 0) radial_acc(32 * (c + 1), v);
+            }
             const int j0 = 32 * c;
             const bool useA = hasA && (!sh.lower || j0 < 32 * tA + 32);
             const bool useB = hasB && (!sh.lower || j0 < 32 * tB + 32);
@@ -316,15 +342,25 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
                     }
         }
     }
+    if constexpr (SEEDED) {
+        __syncthreads();
+        const int X = threadIdx.x >> 6, cl = threadIdx.x & 63, col = col0 + cl;
+        if (X < 2 && col < ncol) {
+            double a = 0.0;
+            for (int g = 0; g < 32; g++) a += rsum[X][g][cl];
+            reinterpret_cast<GLB double *>(glb(aL_in))[2 * (X * nlm + base / 2 + col / 2) + (col & 1)] = a;
+        }
+    }
 }
 
 template <typename T, bool SEEDED>
 __global__ __launch_bounds__(256, (filter_blocks<T, SEEDED>())) void k_filter(Shape sh, const T *__restrict__ FQ, int Kpad,
                                                 int Mpad, int nchq, const int2 *__restrict__ tiles,
                                                 const T *__restrict__ noise, T *__restrict__ phi,
-                                                unsigned long long seed)
+                                                unsigned long long seed, const double *__restrict__ V,
+                                                double2 *__restrict__ aL)
 {
-    body_filter<T, SEEDED>(sh, FQ, Kpad, Mpad, nchq, tiles, noise, phi, seed, blockIdx.x);
+    body_filter<T, SEEDED>(sh, FQ, Kpad, Mpad, nchq, tiles, noise, phi, seed, V, aL, blockIdx.x);
 }
 
 // ------------------------------------------------------- linear radial sum
@@ -339,11 +375,10 @@ __device__ inline void neumaier(double &s, double &c, double v)
     s = t;
 }
 
-template <typename T, bool SEEDED = false>
+template <typename T>
 __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *__restrict__ V_in,
                                                 const T *__restrict__ noise_in,
-                                                double2 *__restrict__ aL_in,
-                                                unsigned long long seed, int bid)
+                                                double2 *__restrict__ aL_in, int bid)
 {
     auto *__restrict__ V = glb(V_in);
     auto *__restrict__ noise = glb(noise_in);
@@ -367,13 +402,7 @@ __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *_
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int j = min(j0 + u, sh.N - 1);
-            if constexpr (!SEEDED) {
-                v[u] = gload(reinterpret_cast<const GLB C2 *>(nz0 + (long long)j * rstride));
-            } else {  // generated from the seed; rounded as a stored noise value would be
-                const double2 g = seeded_noise(seed, idx, j, m0);
-                v[u].x = (T)g.x;
-                v[u].y = (T)g.y;
-            }
+            v[u] = gload(reinterpret_cast<const GLB C2 *>(nz0 + (long long)j * rstride));
             vt[u] = VT[j];
             ve[u] = VE[j];
         }
@@ -393,12 +422,12 @@ __device__ __forceinline__ void body_radial_lin(const Shape &sh, const double *_
     gstore(aL + sh.nlm + idx, make_double2(s[2] + c[2], s[3] + c[3]));
 }
 
-template <typename T, bool SEEDED>
+template <typename T>
 __global__ __launch_bounds__(256) void k_radial_lin(Shape sh, const double *__restrict__ V,
                                                     const T *__restrict__ noise,
-                                                    double2 *__restrict__ aL, unsigned long long seed)
+                                                    double2 *__restrict__ aL)
 {
-    body_radial_lin<T, SEEDED>(sh, V, noise, aL, seed, blockIdx.x);
+    body_radial_lin<T>(sh, V, noise, aL, blockIdx.x);
 }
 
 // -------------------------------------------------------- Legendre synthesis
@@ -1458,7 +1487,7 @@ __global__ __launch_bounds__(256) void g_radial_lin(const GroupItem *__restrict_
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
     if (lb >= (int)((g.sh.nlm + 255) / 256)) return;
-    body_radial_lin<T>(g.sh, g.b.V, (const T *)g.noise, g.b.aL, 0ull, lb);
+    body_radial_lin<T>(g.sh, g.b.V, (const T *)g.noise, g.b.aL, lb);
 }
 
 template <typename T>
@@ -1471,7 +1500,7 @@ __global__ __launch_bounds__(256, (filter_blocks<T, false>())) void g_filter(con
     const GroupItem &g = it[ord[k]];
     if (lb >= g.b.nk1) return;
     body_filter<T>(g.sh, (const T *)g.b.FQ, g.b.Kpad, g.b.Mpad, g.b.nchq, g.b.k1tiles,
-                   (const T *)g.noise, (T *)g.b.phi, 0ull, lb);
+                   (const T *)g.noise, (T *)g.b.phi, 0ull, nullptr, nullptr, lb);
 }
 
 template <typename T, int CF>
@@ -1884,11 +1913,11 @@ static void filter_launch(const Shape &sh, const Bufs &b, const void *noise, voi
     if (sh.fp32)
         hipLaunchKernelGGL((k_filter<float, SEEDED>), grid, dim3(256), 0, s, sh,
                            (const float *)b.FQ, b.Kpad, b.Mpad, b.nchq, b.k1tiles,
-                           (const float *)noise, (float *)phi_out, seed);
+                           (const float *)noise, (float *)phi_out, seed, b.V, b.aL);
     else
         hipLaunchKernelGGL((k_filter<double, SEEDED>), grid, dim3(256), 0, s, sh,
                            (const double *)b.FQ, b.Kpad, b.Mpad, b.nchq, b.k1tiles,
-                           (const double *)noise, (double *)phi_out, seed);
+                           (const double *)noise, (double *)phi_out, seed, b.V, b.aL);
 }
 
 hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void *phi_out,
@@ -1901,26 +1930,15 @@ hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void
     return hipGetLastError();
 }
 
-template <bool SEEDED>
-static void radial_lin_launch(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s,
-                              unsigned long long seed)
+hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s)
 {
     dim3 grid(blocks_for(sh.nlm, 256));
     if (sh.fp32)
-        hipLaunchKernelGGL((k_radial_lin<float, SEEDED>), grid, dim3(256), 0, s, sh, b.V,
-                           (const float *)noise, b.aL, seed);
+        hipLaunchKernelGGL(k_radial_lin<float>, grid, dim3(256), 0, s, sh, b.V,
+                           (const float *)noise, b.aL);
     else
-        hipLaunchKernelGGL((k_radial_lin<double, SEEDED>), grid, dim3(256), 0, s, sh, b.V,
-                           (const double *)noise, b.aL, seed);
-}
-
-hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s,
-                             unsigned long long seed)
-{
-    if (noise)
-        radial_lin_launch<false>(sh, b, noise, s, 0);
-    else
-        radial_lin_launch<true>(sh, b, nullptr, s, seed);
+        hipLaunchKernelGGL(k_radial_lin<double>, grid, dim3(256), 0, s, sh, b.V,
+                           (const double *)noise, b.aL);
     return hipGetLastError();
 }
 

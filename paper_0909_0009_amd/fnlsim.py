@@ -221,7 +221,8 @@ class Simulator:
 
     def forward_seeded(self, seeds, fnl, want_nl=False, device="cuda"):
         """forward(noise(seeds), fnl) with the noise generated inside the
-        kernels instead of stored (bitwise the same result)."""
+        filter instead of stored (a_NL bitwise the same, a_L to FP64
+        rounding)."""
         s = self._seeds(seeds)
         R = s.size
         f = np.ascontiguousarray(np.broadcast_to(np.asarray(fnl, dtype=np.float64), (R,)))

@@ -4,8 +4,9 @@ itself pinned by the generator's published known-answer vectors).
 
 Bars: noise values within a few FP64 ulps of the oracle's (the two sides use
 different log/sin/cos implementations); FP32 noise within one FP32 rounding.
-The seeded forward equals the forward on the materialised noise bit for bit,
-and meets the usual parity bars against the oracle.
+The seeded forward gives the forward on the materialised noise (a_NL bit for
+bit; a_L to FP64 rounding, its radial sum being added in another order inside
+the filter) and meets the usual parity bars against the oracle.
 """
 import numpy as np
 import pytest
@@ -53,6 +54,17 @@ def _check_noise(got, ref, precision, tag):
     print(tag, f"max |diff| {err.max():.2e}", flush=True)
 
 
+def _check_vs_stored(got, base, L, R):
+    """Seeded against stored-noise outputs: a_NL bitwise; a_L (and so a) to
+    FP64 rounding of the same sum."""
+    import torch
+    assert torch.equal(got[2], base[2]) and torch.equal(got[3], base[3])
+    for k in range(R):
+        for g, b, name in zip(got[:2], base[:2], ("aT", "aE")):
+            assert_close(g[k].cpu().numpy(), b[k].cpu().numpy(), L, 1e-13,
+                         f"seeded vs stored {name} r={k}")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_noise_matches_oracle(fs, orc, precision):
     """Several 256-thread blocks with a ragged tail; seeds at both ends of the
@@ -72,11 +84,10 @@ def test_noise_matches_oracle(fs, orc, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_seeded_forward_bitwise_and_oracle(fs, orc, precision):
-    """sim_forward_seeded == sim_forward(sim_noise(seeds)) bit for bit, and
-    both meet the oracle's result on the oracle's noise.  N = 70 spans three
+def test_seeded_forward_vs_stored_and_oracle(fs, orc, precision):
+    """sim_forward_seeded against sim_forward(sim_noise(seeds)), and both
+    against the oracle's result on the oracle's noise.  N = 70 spans three
     32-row filter tiles with a ragged one."""
-    import torch
     L, N = 40, 70
     p = inputs.problem(L, N)
     sim = _sim(fs, p, L, precision)
@@ -84,8 +95,7 @@ def test_seeded_forward_bitwise_and_oracle(fs, orc, precision):
     fnl = [100.0, -35.0]
     got = sim.forward_seeded(seeds, fnl, want_nl=True)
     base = sim.forward(sim.noise(seeds), fnl, want_nl=True)
-    for g, b in zip(got, base):
-        assert torch.equal(g, b)
+    _check_vs_stored(got, base, L, len(seeds))
     P = orc.Problem(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"])
     for k, seed in enumerate(seeds):
         noise = orc.seeded_noise(L, N, seed)
@@ -100,11 +110,10 @@ def test_seeded_forward_bitwise_and_oracle(fs, orc, precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_seeded_paper_scale(fs, orc, precision):
     """Full lmax = 1024, 200 nodes, 1537 x 3072 grid in the benchmark's launch
-    configuration: seeded forward bitwise equal to the stored-noise forward;
+    configuration: seeded forward against the stored-noise forward;
     the noise of the first and last shells against the oracle's generator;
     the outputs against the oracle with transfer tables zeroed except on two
     nodes (as in the stored-noise paper-scale test)."""
-    import torch
     cfg = inputs.CONFIGS["paper"]
     L, N = cfg["lmax"], cfg["nshell"]
     p = inputs.problem(L, N)
@@ -119,8 +128,7 @@ def test_seeded_paper_scale(fs, orc, precision):
     got = sim.forward_seeded([seed], cfg["fnl"], want_nl=True)
     dev_noise = sim.noise([seed])
     base = sim.forward(dev_noise, cfg["fnl"], want_nl=True)
-    for g, b in zip(got, base):
-        assert torch.equal(g, b)
+    _check_vs_stored(got, base, L, 1)
     ref_noise = orc.seeded_noise(L, N, seed)
     for j in (0, 1, N - 1):
         _check_noise(dev_noise[0, j].cpu().numpy().astype(np.complex128)[None],
