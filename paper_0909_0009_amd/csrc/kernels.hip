@@ -1222,6 +1222,11 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     constexpr int NF = RW / 32;
     constexpr int LD = anal_ld<T>();
     __shared__ T lam[RW][LD];
+    // recurrence coefficients (A, B) of the block's RW rows: the two wave
+    // halves run different rows, so a per-lane coefficient read from LDS
+    // (two broadcast addresses per wave) replaces a per-lane select between
+    // two sets of scalar registers
+    __shared__ double2 cab[RW];
     const int L = sh.L, npair = sh.npair, Cpad = sh.Cpad;
     const int4 tl = gload(tiles + bid);
     if (tl.x < 0) return;  // idle slot of the XCD layout
@@ -1238,6 +1243,9 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     const bool hact = lh <= L;
     const long long rowm = mrow(L, m, m);
     const long long srow = (long long)seedoff[m] + (hact ? (lh - m) / kSeedStride : 0);
+    // rows past l = L take the zero padding of m's coefficient block
+    for (int r = lane; r < RW; r += 64) cab[r] = gload(cm_row + (l0w - m) + r);
+    __syncthreads();
     typename M::acc acc[NF][2][CF];
 #pragma unroll
     for (int f = 0; f < NF; f++)
@@ -1281,14 +1289,9 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
                 a0 = sd.y;
                 xp = x[p];
             }
-            // the coefficient rows of both halves have wave-uniform addresses
-            // (scalar loads); each lane keeps its half's
 #pragma unroll 4
             for (int q = 0; q < RW / 2; q++) {
-                const int lA = l0w + q, lB = l0w + RW / 2 + q;
-                // rows past l = L read the zero padding of m's block
-                const double2 cA = gload(cm_row + (lA - m)), cB = gload(cm_row + (lB - m));
-                const double2 ab = half ? cB : cA;
+                const double2 ab = cab[half * (RW / 2) + q];
                 const double v = ab.x * xp * a1 - ab.y * a0;
                 lam[half * (RW / 2) + q][pl] = (T)v;
                 a0 = a1;
