@@ -114,3 +114,17 @@ def test_valid_init_without_gpu_reports_device_error(fs):
     rc, h = _init(fs, 4, 3, r, w, F, a, b)
     assert rc == fs.SIM_EDEVICE
     assert "device" in fs.lib().sim_last_error(None).decode().lower()
+
+
+def test_seed_arguments_are_checked_on_the_host(fs):
+    """Seeds are 64-bit unsigned integers, one per realization; the binding
+    turns anything else into ValueError before a library call."""
+    S = fs.Simulator._seeds
+    got = S([0, 1, 2**40 + 12345, 2**64 - 1])
+    assert got.dtype == np.uint64
+    assert got.tolist() == [0, 1, 2**40 + 12345, 2**64 - 1]
+    assert S(7).tolist() == [7]
+    assert S(np.arange(3, dtype=np.int32)).tolist() == [0, 1, 2]
+    for bad in ([], [-1], [2**64], [1.5], [True], ["3"]):
+        with pytest.raises(ValueError):
+            S(bad)
