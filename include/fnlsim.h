@@ -154,6 +154,12 @@ int sim_forward(sim_ctx *ctx, const void *noise, int R, const double *fnl,
 int sim_noise(sim_ctx *ctx, const unsigned long long *seeds, int R, void *noise);
 int sim_forward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, const double *fnl,
                        void *aT, void *aE, void *aT_nl, void *aE_nl);
+/* sim_backward with the noise regenerated from seeds[0..R) (the reverse pass
+ * only needs it to recompute Phi_L, which then equals sim_backward's bit for
+ * bit).  Arguments and errors as for sim_backward, with seeds (host [R]) in
+ * place of the noise; synchronises the stream like sim_backward. */
+int sim_backward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, const double *fnl,
+                        const void *gT, const void *gE, void *grad_n, double *grad_fnl);
 
 /* Reverse-mode derivative of sim_forward for a real loss.
  *   gT, gE    device [R][n_lm] complex128 cotangents dLoss/dRe a + i dLoss/dIm a

@@ -787,15 +787,17 @@ int sim_noise(sim_ctx *c, const unsigned long long *seeds, int R, void *noise)
 
 // Reverse pass for one realization (the steps of the forward transposed,
 // with Phi_L recomputed from the noise rather than stored).
-static int backward_one(sim_ctx *c, const void *noise, double fnl, const double2 *gT,
-                        const double2 *gE, void *grad, double *fbar_dev)
+// noise == nullptr: Phi_L is recomputed from the noise of realization `seed`,
+// generated inside the filter.
+static int backward_one(sim_ctx *c, const void *noise, unsigned long long seed, double fnl,
+                        const double2 *gT, const double2 *gE, void *grad, double *fbar_dev)
 {
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
     hipStream_t s = c->stream;
     HIPCHECK(c, fnl::launch_radial_adj(sh, b, gT, gE, b.scratch, s));
     HIPCHECK(c, fnl::launch_synth(sh, b, b.scratch, b.G2, s));
-    HIPCHECK(c, fnl::launch_filter(sh, b, noise, b.phi, s));
+    HIPCHECK(c, fnl::launch_filter(sh, b, noise, b.phi, s, seed));
     HIPCHECK(c, fnl::launch_synth(sh, b, b.phi, b.G, s));
     HIPCHECK(c, fnl::launch_ring_adj(sh, b, b.G, b.G2, b.F, b.fpart, fnl, s));
     HIPCHECK(c, fnl::launch_anal(sh, b, b.F, b.phi, 2, s, gT, gE));
@@ -804,8 +806,11 @@ static int backward_one(sim_ctx *c, const void *noise, double fnl, const double2
     return SIM_OK;
 }
 
-int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const void *gT,
-                 const void *gE, void *grad_n, double *grad_fnl)
+// Reverse pass over R realizations: the noise is read from `noise`, or
+// (noise == nullptr) regenerated from seeds[r].
+static int backward_all(sim_ctx *c, const void *noise, const unsigned long long *seeds, int R,
+                        const double *fnl, const void *gT, const void *gE, void *grad_n,
+                        double *grad_fnl)
 {
     if (!c) return SIM_EINVAL;
     if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
@@ -816,7 +821,7 @@ int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const 
             return fail(c, SIM_EINVAL, "n_phi %d is too long for the reverse pass at this precision",
                         c->sh.nphi);
     }
-    if (!noise || !fnl || !gT || !gE || !grad_n || !grad_fnl)
+    if ((!noise && !seeds) || !fnl || !gT || !gE || !grad_n || !grad_fnl)
         return fail(c, SIM_EINVAL, "a required pointer is NULL");
     for (int r = 0; r < R; r++)
         if (!std::isfinite(fnl[r])) return fail(c, SIM_EINVAL, "fnl[%d] is not finite", r);
@@ -838,15 +843,30 @@ int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const 
     }
     const size_t nbytes = (sh.fp32 ? 8 : 16) * (size_t)sh.N * sh.nlm;
     for (int r = 0; r < R; r++) {
-        rc = backward_one(c, (const char *)noise + nbytes * r, fnl[r],
-                          (const double2 *)gT + sh.nlm * r, (const double2 *)gE + sh.nlm * r,
-                          (char *)grad_n + nbytes * r, b.fbar + r);
+        rc = backward_one(c, noise ? (const char *)noise + nbytes * r : nullptr,
+                          noise ? 0ull : seeds[r], fnl[r], (const double2 *)gT + sh.nlm * r,
+                          (const double2 *)gE + sh.nlm * r, (char *)grad_n + nbytes * r,
+                          b.fbar + r);
         if (rc) return rc;
     }
     HIPCHECK(c, hipMemcpyAsync(grad_fnl, b.fbar, sizeof(double) * R, hipMemcpyDeviceToHost,
                                c->stream));
     HIPCHECK(c, hipStreamSynchronize(c->stream));
     return SIM_OK;
+}
+
+int sim_backward(sim_ctx *c, const void *noise, int R, const double *fnl, const void *gT,
+                 const void *gE, void *grad_n, double *grad_fnl)
+{
+    if (c && !noise) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    return backward_all(c, noise, nullptr, R, fnl, gT, gE, grad_n, grad_fnl);
+}
+
+int sim_backward_seeded(sim_ctx *c, const unsigned long long *seeds, int R, const double *fnl,
+                        const void *gT, const void *gE, void *grad_n, double *grad_fnl)
+{
+    if (c && !seeds) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    return backward_all(c, nullptr, seeds, R, fnl, gT, gE, grad_n, grad_fnl);
 }
 
 int sim_debug_stage(sim_ctx *c, int stage, const void *in, void *out)

@@ -22,6 +22,7 @@ SIM_NSTAGE = 6
 STAGE_NAMES = ("radial_lin", "filter", "synth", "ring", "anal", "combine")
 
 EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_backward",
+           "sim_backward_seeded",
            "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
            "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
@@ -71,6 +72,8 @@ def lib():
         L.sim_forward_seeded.restype = ip
         L.sim_noise.argtypes = [vp, vp, ip, vp]
         L.sim_noise.restype = ip
+        L.sim_backward_seeded.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
+        L.sim_backward_seeded.restype = ip
         L.sim_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         L.sim_backward.restype = ip
         L.sim_debug_stage.argtypes = [vp, ip, vp, vp]
@@ -247,6 +250,21 @@ class Simulator:
         gf = np.zeros(R)
         rc = lib().sim_backward(self._h, noise.data_ptr(), R, f.ctypes.data, gT.data_ptr(),
                                 gE.data_ptr(), gn.data_ptr(), gf.ctypes.data)
+        _check(rc, self._h)
+        return gn, gf
+
+    def backward_seeded(self, seeds, fnl, gT, gE, device="cuda"):
+        """backward(noise(seeds), fnl, gT, gE) with the noise regenerated
+        inside the filter instead of stored (bitwise the same result)."""
+        s = self._seeds(seeds)
+        R = s.size
+        f = np.ascontiguousarray(np.broadcast_to(np.asarray(fnl, dtype=np.float64), (R,)))
+        gT = gT.to(torch.complex128).contiguous().reshape(R, self.n_lm)
+        gE = gE.to(torch.complex128).contiguous().reshape(R, self.n_lm)
+        gn = torch.empty((R, self.nshell, self.n_lm), dtype=self.noise_dtype, device=device)
+        gf = np.zeros(R)
+        rc = lib().sim_backward_seeded(self._h, s.ctypes.data, R, f.ctypes.data, gT.data_ptr(),
+                                       gE.data_ptr(), gn.data_ptr(), gf.ctypes.data)
         _check(rc, self._h)
         return gn, gf
 
