@@ -189,3 +189,31 @@ def test_seeded_backward(fs, orc, precision):
     rel = abs(gf_s[0] - ref_gf) / abs(ref_gf)
     print(f"seeded backward {precision}: grad_n {err:.2e} grad_fnl {rel:.2e}", flush=True)
     assert err <= TOL[precision] and rel <= TOL[precision]
+
+
+SEEDED_EDGE = [
+    # (L, N, mean, precision)
+    (1, 1, "sample", "fp64"),      # smallest problem: one shell, l <= 1
+    (2, 3, "ensemble", "fp64"),
+    (17, 7, "sample", "fp32"),     # odd L (no alias term), ragged row and column tiles
+    (33, 65, "ensemble", "fp32"),  # 65 rows: three 32-row tiles, the last of one row
+]
+
+
+@pytest.mark.parametrize("L,N,mean,precision", SEEDED_EDGE)
+def test_seeded_edge_shapes(fs, orc, L, N, mean, precision):
+    p = inputs.problem(L, N)
+    sim = _sim(fs, p, L, precision, mean=mean)
+    seed = 12345 + L
+    got = sim.forward_seeded([seed], 25.0, want_nl=True)
+    base = sim.forward(sim.noise([seed]), 25.0, want_nl=True)
+    _check_vs_stored(got, base, L, 1)
+    noise = orc.seeded_noise(L, N, seed)
+    if precision == "fp32":
+        noise = noise.astype(np.complex64).astype(np.complex128)
+    P = orc.Problem(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                    mean_mode=1 if mean == "ensemble" else 0)
+    ref = P.forward(noise, 25.0)
+    for name, g in zip(("aT", "aE", "aT_nl", "aE_nl"), got):
+        assert_close(g[0].cpu().numpy(), ref[name], L, TOL[precision],
+                     f"seeded edge L={L} N={N} {precision} {name}")
