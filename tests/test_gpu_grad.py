@@ -64,6 +64,7 @@ CASES = [
     (21, 5, 0, 0, "sample", 37.0, "fp64"),       # odd L: no alias, ragged tiles
     (32, 16, 0, 0, "sample", 100.0, "fp32"),
     (32, 16, 0, 0, "ensemble", 100.0, "fp32"),
+    (6, 300, 0, 0, "sample", 60.0, "fp64"),      # N > 256: filter rounds, forward and transposed
 ]
 
 

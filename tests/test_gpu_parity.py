@@ -120,6 +120,7 @@ EDGE = [
     (32, 16, 60, 100, 0, 1),    # larger grid than the minimum
     (40, 33, 0, 0, 0, 2),       # 66 columns (padded tile), two realizations
     (64, 5, 0, 0, 0, 1),        # few shells, many l
+    (6, 300, 0, 0, 0, 1),       # N > 256: the filter runs two rounds of row-tile pairs
 ]
 
 
@@ -160,6 +161,18 @@ def test_paper_scale_sampled_shells(fs, orc, precision):
     got = sim.forward(_dev(noise, precision), cfg["fnl"], want_nl=True)
     ref = _oracle(orc, p, L, alpha=al, beta=be).forward(noise, cfg["fnl"])
     _check_all(got, ref, L, TOL[precision], f"paper {precision}")
+
+
+def test_many_shells_fp32(fs, orc):
+    """N = 300 (10 row tiles, two rounds of tile pairs in the filter, 600
+    columns) on the FP32 path."""
+    L, N = 7, 300
+    p = _problem(L, N)
+    sim = _sim(fs, p, L, "fp32")
+    noise = inputs.noise(L, N, 55).astype(np.complex64).astype(np.complex128)
+    got = sim.forward(_dev(noise, "fp32"), 70.0, want_nl=True)
+    ref = _oracle(orc, p, L).forward(noise, 70.0)
+    _check_all(got, ref, L, TOL["fp32"], "N=300 fp32")
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

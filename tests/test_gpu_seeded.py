@@ -197,6 +197,8 @@ SEEDED_EDGE = [
     (2, 3, "ensemble", "fp64"),
     (17, 7, "sample", "fp32"),     # odd L (no alias term), ragged row and column tiles
     (33, 65, "ensemble", "fp32"),  # 65 rows: three 32-row tiles, the last of one row
+    (6, 300, "sample", "fp32"),    # N > 256: the radial sums come from the first round only
+    (5, 290, "ensemble", "fp64"),
 ]
 
 
