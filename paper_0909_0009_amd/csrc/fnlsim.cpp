@@ -836,6 +836,19 @@ static int backward_all(sim_ctx *c, const void *noise, const unsigned long long 
         b.fpart = (double *)p;
     }
     if (b.fbar_cap < R) {
+        // the old buffer is idle: every reverse pass synchronises its stream
+        // before returning
+        if (b.fbar) {
+            for (size_t i = 0; i < c->allocs.size(); i++)
+                if (c->allocs[i] == b.fbar) {
+                    c->allocs.erase(c->allocs.begin() + i);
+                    break;
+                }
+            c->ws_bytes -= (long long)sizeof(double) * b.fbar_cap;
+            HIPCHECK(c, hipFree(b.fbar));
+            b.fbar = nullptr;
+            b.fbar_cap = 0;
+        }
         void *p = nullptr;
         if ((rc = alloc_zero(c, &p, sizeof(double) * (size_t)R))) return rc;
         b.fbar = (double *)p;

@@ -182,3 +182,24 @@ def test_grad_workload_sampled_shells(fs, orc, precision):
     tol = 1e-10 if precision == "fp64" else 1e-5
     _compare_grad(gn.cpu().numpy().reshape(N, -1).astype(np.complex128), ref_gn, float(gf[0]),
                   ref_gf, L, tol, f"grad workload {precision}")
+
+
+def test_backward_regrows_its_workspace(fs):
+    """R = 1, then R = 2 (the per-realization f_NL workspace grows), then
+    R = 1 again on one context: every call gives the same gradients for the
+    same realization."""
+    import torch
+    L, N = 10, 6
+    p = inputs.problem(L, N)
+    sim = fs.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"])
+    nlm = sim.n_lm
+    n = torch.from_numpy(np.stack([inputs.noise(L, N, 17), inputs.noise(L, N, 18)])).cuda()
+    gT = torch.from_numpy(np.stack([rand_c(nlm, 21), rand_c(nlm, 22)])).cuda()
+    gE = torch.from_numpy(np.stack([rand_c(nlm, 23), rand_c(nlm, 24)])).cuda()
+    gn1, gf1 = sim.backward(n[:1], [40.0], gT[:1], gE[:1])
+    gn2, gf2 = sim.backward(n, [40.0, -15.0], gT, gE)
+    gn3, gf3 = sim.backward(n[:1], [40.0], gT[:1], gE[:1])
+    assert torch.equal(gn1[0], gn2[0]) and torch.equal(gn3, gn1)
+    assert gf1[0] == gf2[0] == gf3[0]
+    ref_gn, ref_gf = sim.backward(n[1:], [-15.0], gT[1:], gE[1:])
+    assert torch.equal(ref_gn[0], gn2[1]) and ref_gf[0] == gf2[1]
