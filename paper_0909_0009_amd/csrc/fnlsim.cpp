@@ -450,9 +450,20 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     for (int m = 0; m <= L; m++)
         seedoff[m + 1] = seedoff[m] + (L - m + 1 + fnl::kSeedStride - 1) / fnl::kSeedStride;
     b.nseedrow = seedoff[L + 1];
+    // filter: a group is the column tiles of one l, which read the same F_l
+    // (x < 0 marks an idle block)
     std::vector<int2> k1;
-    for (int l = 0; l <= L; l++)
-        for (int ct = 0; ct < (2 * (l + 1) + 63) / 64; ct++) k1.push_back(make_int2(l, ct));
+    {
+        std::vector<std::vector<int4>> g1;
+        std::vector<double> w1;
+        for (int l = 0; l <= L; l++) {
+            std::vector<int4> a;
+            for (int ct = 0; ct < (2 * (l + 1) + 63) / 64; ct++) a.push_back(make_int4(l, ct, 0, 0));
+            g1.push_back(a);
+            w1.push_back(1.0);
+        }
+        for (const int4 &e : xcd_layout(g1, w1)) k1.push_back(make_int2(e.x, e.y));
+    }
     b.nk1 = (int)k1.size();
     // synthesis: a group is the pair tiles of one (m, column tile), which read
     // the same Phi_m columns; analysis: the l tiles of one (m, column tile),

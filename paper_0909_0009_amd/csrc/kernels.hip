@@ -148,8 +148,9 @@ __global__ __launch_bounds__(256) void k_noise(Shape sh, unsigned long long seed
 
 // ---------------------------------------------------------------- filter
 
-// Block = (l, 64-column tile), every output row.  Columns are c = 2m +
-// (re/im) of the noise row n[j][idx(l, 0) ..], so a complex coefficient is
+// Block = (l, 64-column tile), every output row; the block table lists the
+// column tiles of one l back to back on one XCD (they share F_l in its L2).
+// Columns are c = 2m + (re/im) of the noise row n[j][idx(l, 0) ..], so a complex coefficient is
 // two real columns and the real filter multiplies both.  Rows come in
 // RT = ceil(N/32) tiles of 32; wave w owns the tile pairs (t, RT-1-t) with
 // t = w, w+4, .. (one pair per wave for N <= 256), so with a lower-triangular
@@ -185,6 +186,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
     using C2 = typename M::c2;
     __shared__ T nz[2][32][kFiltLD];
     const int2 tl = gload(tiles + bx);
+    if (tl.x < 0) return;  // idle slot of the XCD layout (whole block)
     const int l = tl.x, col0 = tl.y * 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int i16 = lane & 15, k4 = lane >> 4;
@@ -1819,6 +1821,7 @@ __global__ __launch_bounds__(256) void k_filter_t(Shape sh, const T *__restrict_
 {
     using M = Mt<T>;
     const int2 tl = tiles[blockIdx.x];
+    if (tl.x < 0) return;  // idle slot of the XCD layout (whole block)
     const int l = tl.x, ct = tl.y;
     const int row0 = blockIdx.y * 64;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
