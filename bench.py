@@ -152,9 +152,22 @@ def time_seeded(torch, sim, cfg, steps, warmup):
     st = sim.profile_read()
     sim.profile(False)
     elem = 8 if sim.precision == "fp32" else 16
+    # the generator alone (sim_noise: one realization's noise written to HBM)
+    nvals = sim.nshell * sim.n_lm
+    buf = sim.noise([1])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(steps):
+        buf = sim.noise([3000 + k])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    gen_ms = e0.elapsed_time(e1) / steps
+    del buf
     return {"value": round(1000.0 / ms, 4), "unit": "maps/s", "ms_per_step": round(ms, 4),
             "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in st.items()},
-            "noise_bytes_not_stored": elem * sim.nshell * sim.n_lm}
+            "noise_bytes_not_stored": elem * nvals,
+            "sim_noise_ms": round(gen_ms, 4),
+            "sim_noise_values_per_s": round(nvals / gen_ms * 1e3, 1)}
 
 
 def time_fwd_bwd(torch, fnlsim, inputs, precision, steps, warmup):
