@@ -130,19 +130,20 @@ __device__ __forceinline__ double2 seeded_noise(unsigned long long seed, long lo
     return make_double2(rad * cs * h, rad * sn * h);
 }
 
-// Grid-stride over the N n_lm values (the grid is capped on the host).
+// x: index idx = l(l+1)/2 + m, y: shell j; grid-stride in both (the grid is
+// capped on the host).  Each thread decodes m = 0 once for all its shells.
 template <typename T>
 __global__ __launch_bounds__(256) void k_noise(Shape sh, unsigned long long seed, T *__restrict__ out)
 {
-    const long long total = (long long)sh.N * sh.nlm;
-    for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < total;
-         t += (long long)gridDim.x * 256) {
-        const int j = (int)(t / sh.nlm);
-        const long long idx = t - (long long)j * sh.nlm;
-        const int l = l_of_index(idx);
-        const double2 g = seeded_noise(seed, idx, j, lm_index(l, 0) == idx);
-        out[2 * t] = (T)g.x;
-        out[2 * t + 1] = (T)g.y;
+    for (long long idx = (long long)blockIdx.x * 256 + threadIdx.x; idx < sh.nlm;
+         idx += (long long)gridDim.x * 256) {
+        const bool m0 = lm_index(l_of_index(idx), 0) == idx;
+        for (int j = blockIdx.y; j < sh.N; j += gridDim.y) {
+            const double2 g = seeded_noise(seed, idx, j, m0);
+            const long long t = (long long)j * sh.nlm + idx;
+            out[2 * t] = (T)g.x;
+            out[2 * t + 1] = (T)g.y;
+        }
     }
 }
 
@@ -1956,9 +1957,9 @@ hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, 
 
 hipError_t launch_noise(const Shape &sh, unsigned long long seed, void *out, hipStream_t s)
 {
-    const long long n = (long long)sh.N * sh.nlm;
-    if (n == 0) return hipSuccess;
-    dim3 grid((unsigned)std::min<long long>(blocks_for(n, 256), 1 << 20));
+    if ((long long)sh.N * sh.nlm == 0) return hipSuccess;
+    dim3 grid((unsigned)std::min<long long>(blocks_for(sh.nlm, 256), 1 << 16),
+              (unsigned)std::min(sh.N, 256));
     if (sh.fp32)
         hipLaunchKernelGGL(k_noise<float>, grid, dim3(256), 0, s, sh, seed, (float *)out);
     else
