@@ -151,14 +151,15 @@ __global__ __launch_bounds__(256) void k_noise(Shape sh, unsigned long long seed
 
 // Block = (l, 64-column tile), every output row; the block table lists the
 // column tiles of one l back to back on one XCD (they share F_l in its L2).
-// Columns are c = 2m + (re/im) of the noise row n[j][idx(l, 0) ..], so a complex coefficient is
-// two real columns and the real filter multiplies both.  Rows come in
-// RT = ceil(N/32) tiles of 32; wave w owns the tile pairs (t, RT-1-t) with
-// t = w, w+4, .. (one pair per wave for N <= 256), so with a lower-triangular
-// F (tile t only needs j < 32 t + 32) the four waves do equal work.  The noise
-// rows of a 32-row K-chunk are staged in LDS, double buffered, and shared by
-// the four waves; the F^T fragments of the next chunk load while the block
-// waits at the chunk's barrier.  The noise is read from HBM once.
+// Columns are c = 2m + (re/im) of the noise row n[j][idx(l, 0) ..], so a
+// complex coefficient is two real columns and the real filter multiplies
+// both.  Rows come in RT = ceil(N/32) tiles of 32, each split into two 16-row
+// halves; the four waves share the halves as described at the round loop, so
+// that with a lower-triangular F (tile t only needs j < 32 t + 32) every
+// chunk gives the waves nearly equal work.  The noise rows of a 32-row
+// K-chunk are staged in LDS, double buffered, and shared by the four waves;
+// the F^T fragments of the next chunk load while the block waits at the
+// chunk's barrier.  The noise is read from HBM once.
 constexpr int kFiltLD = 80;  // LDS row stride (elements): conflict-free B reads
 // blocks per CU the filter's register budget is held to (two: the FP64
 // kernel spills a few registers there and is still faster than at one; the
@@ -195,7 +196,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
     const long long nlm = sh.nlm;
     const long long base = 2 * lm_index(l, 0);
     const auto FQl = FQ + (long long)l * nchq * Mpad * 32;
-    const int RT = (N + 31) / 32, npairs = (RT + 1) / 2;
+    const int RT = (N + 31) / 32;
     // staging role: thread t loads chunk row t / 8, columns 8 (t % 8) .. + 8
     const int sj = threadIdx.x >> 3, sc = (threadIdx.x & 7) * 8;
     auto stage_load = [&](int j0, T (&v)[8]) {
@@ -243,53 +244,60 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
         for (int e = 0; e < 8; e++) rsum[0][sj][sc + e] = rsum[1][sj][sc + e] = 0.0;
     }
 
-    for (int q0 = 0; q0 < npairs; q0 += 4) {
-        const int q = q0 + wave;
-        const int tA = q, tB = RT - 1 - q;
-        const bool hasA = q < npairs, hasB = hasA && tB > tA;
-        // K-chunks this round needs: up to the largest tile of its first pair
-        const int kend = sh.lower ? min(Kpad, 32 * (RT - q0)) : Kpad;
+    // Work unit: a 16-row half tile (t, h).  Units are numbered by descending
+    // t, u = 2 (RT - 1 - t) + h, and dealt round-robin in rounds of 16: wave w
+    // takes u = w, w + 4, w + 8, w + 12.  With a lower-triangular F, chunk c
+    // needs the units with t >= c; dealing them round-robin in descending t
+    // keeps each wave's count of those within one of the other waves', so the
+    // per-chunk barrier costs little imbalance (7 row tiles: 8 tile-chunks of
+    // matrix work on the critical path against 10 for whole tiles).
+    const int nhalf = 2 * RT;
+    for (int u0 = 0; u0 < nhalf; u0 += 16) {
+        int ts[4], hs[4];
+        bool has[4];
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            const int u = u0 + wave + 4 * s;
+            has[s] = u < nhalf;
+            ts[s] = RT - 1 - (u >> 1);
+            hs[s] = u & 1;
+        }
+        // K-chunks this round needs: up to its largest tile
+        const int kend = sh.lower ? min(Kpad, 32 * (RT - (u0 >> 1))) : Kpad;
         const int nchunk = (kend + 31) / 32;
-        typename M::acc acc[2][2][4];
+        typename M::acc acc[4][4];
 #pragma unroll
-        for (int a = 0; a < 2; a++)
+        for (int s = 0; s < 4; s++)
 #pragma unroll
-            for (int h = 0; h < 2; h++)
-#pragma unroll
-                for (int c = 0; c < 4; c++) acc[a][h][c] = typename M::acc{};
-        // F^T fragments of a chunk: [tile][half][K-step]
-        T af[1][2][2][8];
-        // a lane's 8 K-steps of a chunk for one 16-row half: 8 contiguous values
-        auto load_a = [&](int c, T (&A)[2][2][8]) {
+            for (int c = 0; c < 4; c++) acc[s][c] = typename M::acc{};
+        // F^T fragments of a chunk: [unit][K-step]; a lane's 8 K-steps of a
+        // chunk for one 16-row half are 8 contiguous values
+        T af[4][8];
+        auto load_a = [&](int c, T (&A)[4][8]) {
             const auto Fc = FQl + (long long)c * Mpad * 32;
 #pragma unroll
-            for (int a = 0; a < 2; a++) {
-                const int t = a == 0 ? tA : tB;
-                const bool has = a == 0 ? hasA : hasB;
+            for (int s = 0; s < 4; s++) {
+                if (has[s]) {
+                    const auto src = Fc + ((32 * ts[s] + 16 * hs[s] + i16) * 4 + k4) * 8;
+                    using V4 = typename VecOf<typename std::conditional<sizeof(T) == 4, float4, double4>::type>::t;
+                    const V4 lo = *reinterpret_cast<const GLB V4 *>(src);
+                    const V4 hi = *reinterpret_cast<const GLB V4 *>(src + 4);
 #pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    if (has) {
-                        const auto src = Fc + ((32 * t + 16 * h + i16) * 4 + k4) * 8;
-                        using V4 = typename VecOf<typename std::conditional<sizeof(T) == 4, float4, double4>::type>::t;
-                        const V4 lo = *reinterpret_cast<const GLB V4 *>(src);
-                        const V4 hi = *reinterpret_cast<const GLB V4 *>(src + 4);
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            A[a][h][q] = lo[q];
-                            A[a][h][4 + q] = hi[q];
-                        }
-                    } else {
-#pragma unroll
-                        for (int ks = 0; ks < 8; ks++) A[a][h][ks] = T(0);
+                    for (int q = 0; q < 4; q++) {
+                        A[s][q] = lo[q];
+                        A[s][4 + q] = hi[q];
                     }
+                } else {
+#pragma unroll
+                    for (int ks = 0; ks < 8; ks++) A[s][ks] = T(0);
                 }
             }
         };
         T v[8];
         stage_load(0, v);
-        if (q0 == 0) radial_acc(0, v);  // the first round stages every row
+        if (u0 == 0) radial_acc(0, v);  // the first round stages every row
         stage_store(0, v);
-        load_a(0, af[0]);
+        load_a(0, af);
         __syncthreads();
         for (int c = 0; c < nchunk; c++) {
             // MFMAs from LDS buffer c & 1 while the next chunk's noise rows
@@ -298,54 +306,46 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
             const bool more = c + 1 < nchunk;
             if (more) {
                 stage_load(32 * (c + 1), v);
-                if (q0 == 0) radial_acc(32 * (c + 1), v);
+                if (u0 == 0) radial_acc(32 * (c + 1), v);
             }
             const int j0 = 32 * c;
-            const bool useA = hasA && (!sh.lower || j0 < 32 * tA + 32);
-            const bool useB = hasB && (!sh.lower || j0 < 32 * tB + 32);
+            bool use[4];
+#pragma unroll
+            for (int s = 0; s < 4; s++) use[s] = has[s] && (!sh.lower || j0 < 32 * ts[s] + 32);
 #pragma unroll
             for (int ks = 0; ks < 8; ks++) {
                 T bv[4];
 #pragma unroll
                 for (int cf = 0; cf < 4; cf++) bv[cf] = nz[buf][4 * ks + k4][16 * cf + i16];
-                if (useA) {
 #pragma unroll
-                    for (int h = 0; h < 2; h++)
-#pragma unroll
-                        for (int cf = 0; cf < 4; cf++)
-                            acc[0][h][cf] = M::mfma(af[0][0][h][ks], bv[cf], acc[0][h][cf]);
-                }
-                if (useB) {
-#pragma unroll
-                    for (int h = 0; h < 2; h++)
+                for (int s = 0; s < 4; s++) {
+                    if (use[s]) {
 #pragma unroll
                         for (int cf = 0; cf < 4; cf++)
-                            acc[1][h][cf] = M::mfma(af[0][1][h][ks], bv[cf], acc[1][h][cf]);
+                            acc[s][cf] = M::mfma(af[s][ks], bv[cf], acc[s][cf]);
+                    }
                 }
             }
             if (more) {
                 stage_store(buf ^ 1, v);
-                load_a(c + 1, af[0]);
+                load_a(c + 1, af);
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int a = 0; a < 2; a++) {
-            const int t = a == 0 ? tA : tB;
-            if (!(a == 0 ? hasA : hasB)) continue;
+        for (int s = 0; s < 4; s++) {
+            if (!has[s]) continue;
 #pragma unroll
-            for (int h = 0; h < 2; h++)
+            for (int cf = 0; cf < 4; cf++)
 #pragma unroll
-                for (int cf = 0; cf < 4; cf++)
-#pragma unroll
-                    for (int r = 0; r < 4; r++) {
-                        const int row = 32 * t + 16 * h + M::row(k4, r);
-                        const int col = col0 + 16 * cf + i16;
-                        if (row < N && col < ncol) {
-                            const int m = col >> 1;
-                            phi[mrow(sh.L, m, l) * sh.Cpad + 2 * row + (col & 1)] = acc[a][h][cf][r];
-                        }
+                for (int r = 0; r < 4; r++) {
+                    const int row = 32 * ts[s] + 16 * hs[s] + M::row(k4, r);
+                    const int col = col0 + 16 * cf + i16;
+                    if (row < N && col < ncol) {
+                        const int m = col >> 1;
+                        phi[mrow(sh.L, m, l) * sh.Cpad + 2 * row + (col & 1)] = acc[s][cf][r];
                     }
+                }
         }
     }
     if constexpr (SEEDED) {
