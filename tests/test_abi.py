@@ -129,3 +129,15 @@ def test_seed_arguments_are_checked_on_the_host(fs):
     for bad in ([], [-1], [2**64], [1.5], [True], ["3"]):
         with pytest.raises(ValueError):
             S(bad)
+
+
+def test_missing_library_fails_loudly(fs, monkeypatch, tmp_path):
+    """Without libfnlsim.so the binding raises; nothing falls back to another
+    implementation."""
+    monkeypatch.setattr(fs, "_lib", None)
+    monkeypatch.setattr(fs, "LIB_PATH", str(tmp_path / "libfnlsim.so"))
+    with pytest.raises(RuntimeError, match="missing"):
+        fs.lib()
+    r, w, F, a, b = _args()
+    with pytest.raises(RuntimeError, match="missing"):
+        fs.Simulator(4, r, w, F, a, b)
