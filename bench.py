@@ -170,6 +170,39 @@ def time_seeded(torch, sim, cfg, steps, warmup):
             "sim_noise_values_per_s": round(nvals / gen_ms * 1e3, 1)}
 
 
+def time_quadrature(torch, fnlsim, P=2050, ntot=400, n=70, rank=48):
+    """Greedy radial-quadrature design (sim_quadrature_design) at the size of
+    a full design: P = 2 (1024 + 1) problems (l = 0..1024, T and E), a
+    400-shell fine grid, 70 nodes.  Synthetic covariances: rank-48 Gram
+    matrices plus a 1e-3 ridge, built on the GPU; a = the trapezoid rule of a
+    unit grid.  The call is synchronous; the best of 3 after one warm-up."""
+    g = torch.Generator(device="cuda").manual_seed(5)
+    A = torch.randn((P, ntot, rank), dtype=torch.float64, device="cuda", generator=g)
+    cov = torch.bmm(A, A.transpose(1, 2).contiguous()) / rank
+    cov += 1e-3 * torch.eye(ntot, dtype=torch.float64, device="cuda")
+    del A
+    a = torch.ones((P, ntot), dtype=torch.float64, device="cuda")
+    a[:, 0] = a[:, -1] = 0.5
+    torch.cuda.synchronize()
+    fnlsim.quadrature_design(cov, a, n)
+    best = float("inf")
+    for _ in range(3):
+        t0 = time.perf_counter()
+        nodes, err, _ = fnlsim.quadrature_design(cov, a, n)
+        best = min(best, time.perf_counter() - t0)
+    del cov, a
+    # algorithmic bytes: C read once (b = C a), then per step k the gain
+    # reads (d, e), the update reads k earlier columns, row sel of C and
+    # (d, e), and writes column k, d and e
+    pn = 8.0 * P * ntot
+    byts = pn * ntot + sum(pn * (2 + k + 1 + 2 + 3) for k in range(n))
+    return {"ms": round(best * 1e3, 3), "problems": P, "fine_shells": ntot, "nodes": n,
+            "algorithmic_bytes": byts, "achieved_GBps": round(byts / best / 1e9, 1),
+            "final_error_rel": float(err[-1] / (err[0] + 1e-300)),
+            "workload": "rank-48 Gram covariances + 1e-3 ridge (synthetic), P = 2050, "
+                        "400-shell fine grid, 70 greedy nodes"}
+
+
 def time_fwd_bwd(torch, fnlsim, inputs, precision, steps, warmup):
     """Forward + hand-written reverse pass per step at the differentiation
     workload (lmax 512, 96 nodes, 769 x 1536 grid), one realization."""
@@ -310,6 +343,8 @@ def main():
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB first (counter calibration)")
     ap.add_argument("--no-grad", action="store_true", help="skip the fwd+bwd leg (lmax 512)")
+    ap.add_argument("--no-quad", action="store_true",
+                    help="skip the radial-quadrature design leg")
     ap.add_argument("--no-seeded", action="store_true",
                     help="skip the counter-based-noise forward leg")
     ap.add_argument("--batch", action="store_true",
@@ -381,6 +416,11 @@ def main():
             grad["fp64"] = time_fwd_bwd(torch, fnlsim, inputs, "fp64", args.steps, args.warmup)
         log(f"fwd+bwd: {grad}")
         torch.cuda.empty_cache()
+    quad = None
+    if not args.no_quad:
+        quad = time_quadrature(torch, fnlsim)
+        log(f"quadrature design: {quad['ms']} ms")
+        torch.cuda.empty_cache()
     batch = None
     if args.batch:
         batch = {"fp32": time_batch(torch, fnlsim, inputs, "fp32", args.steps, args.warmup)}
@@ -416,6 +456,7 @@ def main():
         "fp64": fp64,
         "mixed_vs_fp64_max_rel_err": err,
         "seeded": seeded,
+        "quadrature_design": quad,
         "fwd_bwd": grad,
         "batch": batch,
         "cpu_baseline": cpu,

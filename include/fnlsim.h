@@ -161,6 +161,32 @@ int sim_forward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, con
 int sim_backward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, const double *fnl,
                         const void *gT, const void *gE, void *grad_n, double *grad_fnl);
 
+/* Greedy design of the radial quadrature (Sect. 3: Eq. mean_err and the
+ * linear system for the optimal weights).  For each of P problems (a
+ * multipole and a transfer table), the line-of-sight integral is the fine sum
+ * I = sum_k a_k Phi(r_k) over ntot shells with Phi ~ N(0, C); a node set S
+ * with optimal weights (C_SS w = (C a)_S) leaves the expected quadratic error
+ * a^T C a - w^T C_SS w.  Starting from S empty, each step adds the shell that
+ * most lowers the sum of those errors over all problems (T and E problems
+ * enter with equal weight; scale C and a beforehand to weight them
+ * otherwise); ties go to the lowest index.
+ *   cov     device [P][ntot][ntot] FP64, symmetric positive definite
+ *   a       device [P][ntot] FP64 fine-sum weights (dr_k r_k^2 X(r_k))
+ *   n       nodes to choose, 1 <= n <= min(ntot, 1024); 1 <= P <= 65535,
+ *           ntot <= 16384
+ *   nodes   host [n] out: fine-grid index of the node chosen at each step
+ *   err     host [n] out: summed optimal error after each step
+ *   w       device [P][n] FP64 out: optimal weights of the n nodes, in the
+ *           order of `nodes`
+ *   stream  HIP stream (NULL = default)
+ * Synchronous.  SIM_EINVAL for a null pointer or sizes out of range (nothing
+ * launched), SIM_ENOMEM if the workspace (8 P n ntot bytes and a little more)
+ * cannot be allocated, SIM_EDEVICE if a HIP call fails; the message is in
+ * sim_last_error(NULL).  A shell whose conditional variance has vanished in a
+ * problem contributes nothing there and gets weight 0 in that problem. */
+int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
+                          int *nodes, double *err, double *w, void *stream);
+
 /* Reverse-mode derivative of sim_forward for a real loss.
  *   gT, gE    device [R][n_lm] complex128 cotangents dLoss/dRe a + i dLoss/dIm a
  *   grad_n    device [R][N][n_lm] complex, dtype of the noise, same convention

@@ -21,6 +21,7 @@
 
 #include "../../include/fnlsim.h"
 #include "internal.h"
+#include "quadrature.h"
 
 using fnl::Bufs;
 using fnl::Shape;
@@ -1106,6 +1107,89 @@ int sim_batch_forward(sim_batch *b, const void *const *noise, const double *fnl,
         (e = hipStreamWaitEvent(b->user, b->ev_out, 0)) != hipSuccess)
         return batch_fail(b, SIM_EDEVICE, "graph launch", e);
     return SIM_OK;
+}
+
+int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
+                          int *nodes, double *err, double *w, void *stream)
+{
+    if (!cov || !a || !nodes || !err || !w)
+        return fail(nullptr, SIM_EINVAL, "a required pointer is NULL");
+    if (P < 1 || P > 65535) return fail(nullptr, SIM_EINVAL, "P = %d outside [1, 65535]", P);
+    if (ntot < 1 || ntot > 16384)
+        return fail(nullptr, SIM_EINVAL, "ntot = %d outside [1, 16384]", ntot);
+    if (n < 1 || n > ntot || n > 1024)
+        return fail(nullptr, SIM_EINVAL, "n = %d outside [1, min(ntot, 1024)]", n);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t pn = (size_t)P * ntot;
+    const size_t nd = 2 * pn + (size_t)P * n * ntot + 2 * (size_t)P + 2 * (size_t)P * n + ntot + P;
+    double *ws = nullptr;
+    unsigned char *chosen = nullptr;
+    int *nodes_dev = nullptr;
+    int rc = SIM_OK;
+    std::vector<double> gain(ntot), aca(P);
+    std::vector<char> used(ntot, 0);
+    fnl::QuadState q{};
+    double E = 0.0;
+    auto release = [&]() {
+        if (ws) (void)hipFree(ws);
+        if (chosen) (void)hipFree(chosen);
+        if (nodes_dev) (void)hipFree(nodes_dev);
+    };
+#define QCHECK(call)                                                                           \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess) {                                                                \
+            rc = fail(nullptr, SIM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
+            goto done;                                                                         \
+        }                                                                                      \
+    } while (0)
+    if (hipMalloc(&ws, nd * sizeof(double)) != hipSuccess ||
+        hipMalloc(&chosen, (size_t)ntot) != hipSuccess ||
+        hipMalloc(&nodes_dev, sizeof(int) * (size_t)n) != hipSuccess) {
+        release();
+        return fail(nullptr, SIM_ENOMEM, "workspace allocation failed (%zu bytes)",
+                    nd * sizeof(double));
+    }
+    q.P = P;
+    q.ntot = ntot;
+    q.nmax = n;
+    q.C = cov;
+    q.a = a;
+    q.e = ws;
+    q.d = q.e + pn;
+    q.V = q.d + pn;
+    q.piv = q.V + (size_t)P * n * ntot;
+    q.z = q.piv + 2 * (size_t)P;
+    q.diag = q.z + (size_t)P * n;
+    q.gain = q.diag + (size_t)P * n;
+    q.aCa = q.gain + ntot;
+    QCHECK(hipMemsetAsync(chosen, 0, (size_t)ntot, s));
+    QCHECK(fnl::quad_init(q, s));
+    QCHECK(hipMemcpyAsync(aca.data(), q.aCa, sizeof(double) * P, hipMemcpyDeviceToHost, s));
+    QCHECK(hipStreamSynchronize(s));
+    for (int p = 0; p < P; p++) E += aca[p];
+    for (int k = 0; k < n; k++) {
+        QCHECK(fnl::quad_gain(q, chosen, s));
+        QCHECK(hipMemcpyAsync(gain.data(), q.gain, sizeof(double) * ntot, hipMemcpyDeviceToHost, s));
+        QCHECK(hipStreamSynchronize(s));
+        // the largest gain among the shells not yet chosen (lowest index on ties)
+        int best = -1;
+        for (int j = 0; j < ntot; j++)
+            if (!used[j] && (best < 0 || gain[j] > gain[best])) best = j;
+        nodes[k] = best;
+        used[best] = 1;
+        E -= gain[best];
+        err[k] = E;
+        QCHECK(hipMemsetAsync(chosen + best, 1, 1, s));
+        QCHECK(fnl::quad_step(q, best, k, s));
+    }
+    QCHECK(hipMemcpyAsync(nodes_dev, nodes, sizeof(int) * n, hipMemcpyHostToDevice, s));
+    QCHECK(fnl::quad_weights(q, nodes_dev, n, w, s));
+    QCHECK(hipStreamSynchronize(s));
+done:
+#undef QCHECK
+    release();
+    return rc;
 }
 
 }  // extern "C"

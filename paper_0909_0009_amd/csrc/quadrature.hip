@@ -1,0 +1,160 @@
+// quadrature.hip -- greedy design of the radial quadrature (Sect. 3).
+//
+// For P problems (a multipole and a transfer table each) on one fine grid of
+// ntot shells, the expected error of I_hat = sum_i w_i Phi(r_i) over a node set
+// S with its optimal weights (Eq. mean_err and the optimal-weight equations
+// C_SS w = (C a)_S) is  a^T C a - b_S^T C_SS^{-1} b_S,  b = C a.  Growing S by
+// one shell j lowers it by  (b_j - v_j . z)^2 / (C_jj - |v_j|^2),  where
+// C_SS = L L^T, v_j = L^{-1} C_Sj and z = L^{-1} b_S: an incremental Cholesky
+// factorisation.  Every step sums that gain over the problems for every
+// candidate shell (one block per shell), the host picks the best shell, and
+// one more column of L is formed for every (problem, shell) at once.
+#include <hip/hip_runtime.h>
+
+#include "quadrature.h"
+
+namespace fnl {
+
+namespace {
+
+// b = C a (C symmetric: b_j = sum_k C_kj a_k, so adjacent threads read
+// adjacent j of row k), e = b, d = diag(C); one block per (256 shells, problem)
+__global__ __launch_bounds__(256) void k_quad_init(QuadState q)
+{
+    const int p = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= q.ntot) return;
+    const double *Cp = q.C + (long long)p * q.ntot * q.ntot;
+    const double *ap = q.a + (long long)p * q.ntot;
+    double b = 0.0;
+    for (int k = 0; k < q.ntot; k++) b += Cp[(long long)k * q.ntot + j] * ap[k];
+    q.e[(long long)p * q.ntot + j] = b;
+    q.d[(long long)p * q.ntot + j] = Cp[(long long)j * q.ntot + j];
+}
+
+// a^T C a = a . b per problem (one block per problem, fixed summation order)
+__global__ __launch_bounds__(256) void k_quad_aca(QuadState q)
+{
+    __shared__ double part[256];
+    const int p = blockIdx.x;
+    const double *ap = q.a + (long long)p * q.ntot;
+    const double *bp = q.e + (long long)p * q.ntot;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < q.ntot; j += 256) s += ap[j] * bp[j];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q.aCa[p] = part[0];
+}
+
+// gain_j = sum_p e_pj^2 / d_pj over the problems (chosen shells: 0; a shell
+// whose conditional variance has vanished in a problem adds nothing there).
+// One block per shell, threads over the problems, a fixed-order tree sum.
+__global__ __launch_bounds__(256) void k_quad_gain(QuadState q, const unsigned char *chosen)
+{
+    __shared__ double part[256];
+    const int j = blockIdx.x;
+    double g = 0.0;
+    if (!chosen[j]) {
+        for (int p = threadIdx.x; p < q.P; p += 256) {
+            const double dj = q.d[(long long)p * q.ntot + j];
+            const double ej = q.e[(long long)p * q.ntot + j];
+            if (dj > 0.0) g += ej * ej / dj;
+        }
+    }
+    part[threadIdx.x] = g;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) q.gain[j] = part[0];
+}
+
+// the chosen shell's (d, e) per problem, read before the step overwrites them
+__global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, int sel, int k)
+{
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= q.P) return;
+    const double dd = q.d[(long long)p * q.ntot + sel];
+    const double ee = q.e[(long long)p * q.ntot + sel];
+    q.piv[2 * p] = dd;
+    q.piv[2 * p + 1] = ee;
+    const double l = dd > 0.0 ? sqrt(dd) : 0.0;
+    q.diag[(long long)p * q.nmax + k] = l;
+    q.z[(long long)p * q.nmax + k] = l > 0.0 ? ee / l : 0.0;
+}
+
+// column k of L for every shell j: v_j[k] = (C_j,sel - sum_{i<k} v_j[i] v_sel[i]) / l,
+// then d_j -= v_j[k]^2 and e_j -= v_j[k] z_k
+__global__ __launch_bounds__(256) void k_quad_update(QuadState q, int sel, int k)
+{
+    const int p = blockIdx.y;
+    const int j = blockIdx.x * 256 + threadIdx.x;
+    if (j >= q.ntot) return;
+    const long long n2 = (long long)q.ntot;
+    const double *Vp = q.V + (long long)p * q.nmax * n2;
+    const double l = q.diag[(long long)p * q.nmax + k];
+    double v = 0.0;
+    if (l > 0.0) {
+        double dot = 0.0;
+        for (int i = 0; i < k; i++) dot += Vp[i * n2 + j] * Vp[i * n2 + sel];
+        v = (q.C[(long long)p * n2 * n2 + (long long)sel * n2 + j] - dot) / l;
+    }
+    q.V[(long long)p * q.nmax * n2 + (long long)k * n2 + j] = v;
+    const long long ij = (long long)p * n2 + j;
+    q.d[ij] -= v * v;
+    q.e[ij] -= v * q.z[(long long)p * q.nmax + k];
+}
+
+// optimal weights: L^T w = z by back substitution, L[k][i] = v_{node k}[i]
+// (i < k) and L[k][k] = diag[k]; one thread per problem
+__global__ __launch_bounds__(64) void k_quad_weights(QuadState q, const int *nodes, int n, double *w)
+{
+    const int p = blockIdx.x * 64 + threadIdx.x;
+    if (p >= q.P) return;
+    const long long n2 = (long long)q.ntot;
+    const double *Vp = q.V + (long long)p * q.nmax * n2;
+    double *wp = w + (long long)p * n;
+    for (int k = n - 1; k >= 0; k--) {
+        double s = q.z[(long long)p * q.nmax + k];
+        for (int i = k + 1; i < n; i++) s -= Vp[(long long)k * n2 + nodes[i]] * wp[i];
+        const double l = q.diag[(long long)p * q.nmax + k];
+        wp[k] = l > 0.0 ? s / l : 0.0;
+    }
+}
+
+unsigned blocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+hipError_t quad_init(const QuadState &q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_init, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q);
+    hipLaunchKernelGGL(k_quad_aca, dim3(q.P), dim3(256), 0, s, q);
+    return hipGetLastError();
+}
+
+hipError_t quad_gain(const QuadState &q, const unsigned char *chosen, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_gain, dim3(q.ntot), dim3(256), 0, s, q, chosen);
+    return hipGetLastError();
+}
+
+hipError_t quad_step(const QuadState &q, int sel, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, sel, k);
+    hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q, sel, k);
+    return hipGetLastError();
+}
+
+hipError_t quad_weights(const QuadState &q, const int *nodes_dev, int n, double *w, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_weights, dim3(blocks(q.P, 64)), dim3(64), 0, s, q, nodes_dev, n, w);
+    return hipGetLastError();
+}
+
+}  // namespace fnl

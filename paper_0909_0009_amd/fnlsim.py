@@ -22,7 +22,7 @@ SIM_NSTAGE = 6
 STAGE_NAMES = ("radial_lin", "filter", "synth", "ring", "anal", "combine")
 
 EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_backward",
-           "sim_backward_seeded",
+           "sim_backward_seeded", "sim_quadrature_design",
            "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
            "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
@@ -72,6 +72,8 @@ def lib():
         L.sim_forward_seeded.restype = ip
         L.sim_noise.argtypes = [vp, vp, ip, vp]
         L.sim_noise.restype = ip
+        L.sim_quadrature_design.argtypes = [vp, vp, ip, ip, ip, vp, vp, vp, vp]
+        L.sim_quadrature_design.restype = ip
         L.sim_backward_seeded.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         L.sim_backward_seeded.restype = ip
         L.sim_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
@@ -111,6 +113,30 @@ def _check(rc, ctx):
 
 def nlm(L):
     return (L + 1) * (L + 2) // 2
+
+
+def quadrature_design(cov, a, n, stream=None):
+    """Greedy radial-quadrature design (sim_quadrature_design).
+    cov: CUDA float64 [P][ntot][ntot]; a: CUDA float64 [P][ntot].
+    Returns (nodes int32 [n], err float64 [n], w CUDA float64 [P][n])."""
+    if cov.dtype != torch.float64 or a.dtype != torch.float64 or not cov.is_cuda or not a.is_cuda:
+        raise TypeError("cov and a must be CUDA float64 tensors")
+    cov = cov.contiguous()
+    a = a.contiguous()
+    if cov.dim() != 3 or cov.shape[1] != cov.shape[2] or tuple(a.shape) != tuple(cov.shape[:2]):
+        raise ValueError("cov must be [P][ntot][ntot] and a [P][ntot]")
+    P, ntot = int(cov.shape[0]), int(cov.shape[1])
+    n = int(n)
+    nodes = np.zeros(n, dtype=np.int32)
+    err = np.zeros(n)
+    w = torch.empty((P, n), dtype=torch.float64, device=cov.device)
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    rc = lib().sim_quadrature_design(cov.data_ptr(), a.data_ptr(), P, ntot, n,
+                                     nodes.ctypes.data, err.ctypes.data, w.data_ptr(),
+                                     ctypes.c_void_p(stream) if stream else None)
+    _check(rc, None)
+    return nodes, err, w
 
 
 class Simulator:

@@ -100,6 +100,7 @@ def test_null_context_calls(fs):
     assert L.sim_forward_seeded(None, None, 1, None, None, None, None, None) == fs.SIM_EINVAL
     assert L.sim_noise(None, None, 1, None) == fs.SIM_EINVAL
     assert L.sim_backward_seeded(None, None, 1, None, None, None, None, None) == fs.SIM_EINVAL
+    assert L.sim_quadrature_design(None, None, 1, 4, 2, None, None, None, None) == fs.SIM_EINVAL
     assert L.sim_debug_stage(None, 1, None, None) == fs.SIM_EINVAL
     assert L.sim_get_info(None, None) == fs.SIM_EINVAL
     h = ctypes.c_void_p()

@@ -1,0 +1,96 @@
+"""GPU greedy radial-quadrature design (sim_quadrature_design) against the
+FP64 oracle of Sect. 3 (oracle/quadrature.py): the nodes bit for bit (an
+index decision, taken in FP64 on both sides), the summed error after every
+step and the optimal weights."""
+import numpy as np
+import pytest
+
+from paper_0909_0009_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fs():
+    import torch
+    from paper_0909_0009_amd import build, fnlsim
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    if not __import__("os").path.exists(fnlsim.LIB_PATH):
+        build.build()
+    fnlsim.lib()
+    return fnlsim
+
+
+def _spd(n, rng):
+    A = rng.standard_normal((n, n))
+    return A @ A.T / n + 0.05 * np.eye(n)
+
+
+def _compare(fs, probs, n, tag):
+    import torch
+    from oracle import quadrature as q
+    cov = torch.from_numpy(np.stack([C for C, _ in probs])).cuda()
+    a = torch.from_numpy(np.stack([x for _, x in probs])).cuda()
+    nodes, err, w = fs.quadrature_design(cov, a, n)
+    ref_nodes, ref_err = q.greedy_nodes(probs, n)
+    assert nodes.tolist() == ref_nodes, f"{tag}: {nodes.tolist()} vs {ref_nodes}"
+    rel = np.max(np.abs(err - np.array(ref_err)) / np.abs(np.array(ref_err)))
+    assert rel <= 1e-9, f"{tag}: error curve off by {rel:.2e}"
+    wg = w.cpu().numpy()
+    werr = 0.0
+    for p, (C, x) in enumerate(probs):
+        ref_w = q.optimal_weights(C, x, ref_nodes)
+        werr = max(werr, np.max(np.abs(wg[p] - ref_w)) / np.max(np.abs(ref_w)))
+    assert werr <= 1e-8, f"{tag}: weights off by {werr:.2e}"
+    print(tag, f"nodes equal, error curve {rel:.1e}, weights {werr:.1e}", flush=True)
+
+
+@pytest.mark.parametrize("P,ntot,n,seed", [(5, 300, 9, 1), (1, 37, 37, 2), (3, 64, 1, 3)])
+def test_random_problems(fs, P, ntot, n, seed):
+    """Random SPD covariances: a ragged 300-shell grid, every shell chosen
+    (n = ntot: the last error is 0 up to rounding), and a single node."""
+    rng = np.random.default_rng(seed)
+    probs = [(_spd(ntot, rng), rng.standard_normal(ntot)) for _ in range(P)]
+    if n == ntot:
+        import torch
+        cov = torch.from_numpy(np.stack([C for C, _ in probs])).cuda()
+        a = torch.from_numpy(np.stack([x for _, x in probs])).cuda()
+        nodes, err, w = fs.quadrature_design(cov, a, n)
+        assert sorted(nodes.tolist()) == list(range(ntot))
+        total = sum(float(x @ C @ x) for C, x in probs)
+        assert abs(err[-1]) <= 1e-9 * total
+        # with every shell a node the optimal weights are the fine weights
+        wg = w.cpu().numpy()[0]
+        assert np.allclose(wg, probs[0][1][nodes], rtol=1e-7, atol=1e-9)
+        return
+    _compare(fs, probs, n, f"P={P} ntot={ntot} n={n}")
+
+
+def test_design_on_the_synthetic_inputs(fs):
+    """T and E problems for l = 2..5 on a 48-shell grid of the synthetic
+    covariance and transfer tables, each scaled to unit a^T C a, 12 nodes."""
+    from oracle import quadrature as q
+    L = 5
+    r = np.linspace(13000.0, 15000.0, 48)
+    C = inputs.covariance(L, r)
+    alpha, beta = inputs.transfer_tables(L, r)
+    probs = []
+    for l in range(2, L + 1):
+        for X in (alpha, beta):
+            x = q.fine_weights(r, X[l])
+            s = float(x @ C[l] @ x)
+            probs.append((C[l] / s, x))
+    _compare(fs, probs, 12, "synthetic l=2..5")
+
+
+def test_bad_arguments(fs):
+    import torch
+    cov = torch.eye(4, dtype=torch.float64, device="cuda")[None]
+    a = torch.ones((1, 4), dtype=torch.float64, device="cuda")
+    with pytest.raises(fs.SimError):
+        fs.quadrature_design(cov, a, 5)      # n > ntot
+    with pytest.raises(fs.SimError):
+        fs.quadrature_design(cov, a, 0)
+    with pytest.raises(TypeError):
+        fs.quadrature_design(cov.float(), a, 2)
