@@ -1121,15 +1121,15 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
         return fail(nullptr, SIM_EINVAL, "n = %d outside [1, min(ntot, 1024)]", n);
     hipStream_t s = (hipStream_t)stream;
     const size_t pn = (size_t)P * ntot;
-    const size_t nd = 2 * pn + (size_t)P * n * ntot + 2 * (size_t)P + 2 * (size_t)P * n + ntot + P;
+    // e, d, V, piv, z, diag, gain, aCa, then the error curve and the running error
+    const size_t nd = 2 * pn + (size_t)P * n * ntot + 2 * (size_t)P + 2 * (size_t)P * n + ntot + P +
+                      (size_t)n + 1;
     double *ws = nullptr;
     unsigned char *chosen = nullptr;
     int *nodes_dev = nullptr;
     int rc = SIM_OK;
-    std::vector<double> gain(ntot), aca(P);
-    std::vector<char> used(ntot, 0);
     fnl::QuadState q{};
-    double E = 0.0;
+    double *err_dev = nullptr, *E_dev = nullptr;
     auto release = [&]() {
         if (ws) (void)hipFree(ws);
         if (chosen) (void)hipFree(chosen);
@@ -1163,28 +1163,21 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
     q.diag = q.z + (size_t)P * n;
     q.gain = q.diag + (size_t)P * n;
     q.aCa = q.gain + ntot;
+    err_dev = q.aCa + P;
+    E_dev = err_dev + n;
     QCHECK(hipMemsetAsync(chosen, 0, (size_t)ntot, s));
     QCHECK(fnl::quad_init(q, s));
-    QCHECK(hipMemcpyAsync(aca.data(), q.aCa, sizeof(double) * P, hipMemcpyDeviceToHost, s));
-    QCHECK(hipStreamSynchronize(s));
-    for (int p = 0; p < P; p++) E += aca[p];
+    QCHECK(fnl::quad_total(q, E_dev, s));
+    // every step runs on the device: gains, the choice (largest gain among
+    // the shells not yet chosen, lowest index on ties), the Cholesky column
     for (int k = 0; k < n; k++) {
         QCHECK(fnl::quad_gain(q, chosen, s));
-        QCHECK(hipMemcpyAsync(gain.data(), q.gain, sizeof(double) * ntot, hipMemcpyDeviceToHost, s));
-        QCHECK(hipStreamSynchronize(s));
-        // the largest gain among the shells not yet chosen (lowest index on ties)
-        int best = -1;
-        for (int j = 0; j < ntot; j++)
-            if (!used[j] && (best < 0 || gain[j] > gain[best])) best = j;
-        nodes[k] = best;
-        used[best] = 1;
-        E -= gain[best];
-        err[k] = E;
-        QCHECK(hipMemsetAsync(chosen + best, 1, 1, s));
-        QCHECK(fnl::quad_step(q, best, k, s));
+        QCHECK(fnl::quad_select(q, chosen, nodes_dev, err_dev, E_dev, k, s));
+        QCHECK(fnl::quad_step(q, nodes_dev, k, s));
     }
-    QCHECK(hipMemcpyAsync(nodes_dev, nodes, sizeof(int) * n, hipMemcpyHostToDevice, s));
     QCHECK(fnl::quad_weights(q, nodes_dev, n, w, s));
+    QCHECK(hipMemcpyAsync(nodes, nodes_dev, sizeof(int) * n, hipMemcpyDeviceToHost, s));
+    QCHECK(hipMemcpyAsync(err, err_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     QCHECK(hipStreamSynchronize(s));
 done:
 #undef QCHECK

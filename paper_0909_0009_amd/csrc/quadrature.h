@@ -24,8 +24,14 @@ struct QuadState {
 };
 
 hipError_t quad_init(const QuadState &q, hipStream_t s);
+// *E = sum_p a^T C a
+hipError_t quad_total(const QuadState &q, double *E, hipStream_t s);
 hipError_t quad_gain(const QuadState &q, const unsigned char *chosen, hipStream_t s);
-hipError_t quad_step(const QuadState &q, int sel, int k, hipStream_t s);
+// step k: sels[k] = best unchosen shell (lowest index on ties), chosen[sels[k]] = 1,
+// *E -= its gain, err[k] = *E (all device memory)
+hipError_t quad_select(const QuadState &q, unsigned char *chosen, int *sels, double *err, double *E,
+                       int k, hipStream_t s);
+hipError_t quad_step(const QuadState &q, const int *sels, int k, hipStream_t s);
 hipError_t quad_weights(const QuadState &q, const int *nodes_dev, int n, double *w, hipStream_t s);
 
 }  // namespace fnl

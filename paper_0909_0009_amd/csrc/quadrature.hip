@@ -7,8 +7,9 @@
 // one shell j lowers it by  (b_j - v_j . z)^2 / (C_jj - |v_j|^2),  where
 // C_SS = L L^T, v_j = L^{-1} C_Sj and z = L^{-1} b_S: an incremental Cholesky
 // factorisation.  Every step sums that gain over the problems for every
-// candidate shell (one block per shell), the host picks the best shell, and
-// one more column of L is formed for every (problem, shell) at once.
+// candidate shell (one block per shell), picks the best shell on the device,
+// and forms one more column of L for every (problem, shell) at once; the
+// host only launches.
 #include <hip/hip_runtime.h>
 
 #include "quadrature.h"
@@ -74,11 +75,68 @@ __global__ __launch_bounds__(256) void k_quad_gain(QuadState q, const unsigned c
     if (threadIdx.x == 0) q.gain[j] = part[0];
 }
 
+// E = sum_p a^T C a (one block, fixed order)
+__global__ __launch_bounds__(256) void k_quad_total(QuadState q, double *E)
+{
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int p = threadIdx.x; p < q.P; p += 256) s += q.aCa[p];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *E = part[0];
+}
+
+// step k's node: the largest gain among the shells not yet chosen, the lowest
+// index on ties (one block); records it, marks it chosen and lowers the
+// running error E by its gain
+__global__ __launch_bounds__(256) void k_quad_select(QuadState q, unsigned char *chosen, int *sel,
+                                                     double *err, double *E, int k)
+{
+    __shared__ double gv[256];
+    __shared__ int gi[256];
+    double best = 0.0;
+    int bi = -1;
+    for (int j = threadIdx.x; j < q.ntot; j += 256) {
+        if (chosen[j]) continue;
+        const double g = q.gain[j];
+        if (bi < 0 || g > best) {  // j ascending: a tie keeps the lower index
+            best = g;
+            bi = j;
+        }
+    }
+    gv[threadIdx.x] = best;
+    gi[threadIdx.x] = bi;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) {
+            const int o = gi[threadIdx.x + h], m = gi[threadIdx.x];
+            const double go = gv[threadIdx.x + h], gm = gv[threadIdx.x];
+            if (o >= 0 && (m < 0 || go > gm || (go == gm && o < m))) {
+                gv[threadIdx.x] = go;
+                gi[threadIdx.x] = o;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const int s = gi[0];  // n <= ntot: an unchosen shell always exists
+        sel[k] = s;
+        chosen[s] = 1;
+        *E -= gv[0];
+        err[k] = *E;
+    }
+}
+
 // the chosen shell's (d, e) per problem, read before the step overwrites them
-__global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, int sel, int k)
+__global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, const int *sels, int k)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= q.P) return;
+    const int sel = sels[k];
     const double dd = q.d[(long long)p * q.ntot + sel];
     const double ee = q.e[(long long)p * q.ntot + sel];
     q.piv[2 * p] = dd;
@@ -90,11 +148,12 @@ __global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, int sel, int k)
 
 // column k of L for every shell j: v_j[k] = (C_j,sel - sum_{i<k} v_j[i] v_sel[i]) / l,
 // then d_j -= v_j[k]^2 and e_j -= v_j[k] z_k
-__global__ __launch_bounds__(256) void k_quad_update(QuadState q, int sel, int k)
+__global__ __launch_bounds__(256) void k_quad_update(QuadState q, const int *sels, int k)
 {
     const int p = blockIdx.y;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= q.ntot) return;
+    const int sel = sels[k];
     const long long n2 = (long long)q.ntot;
     const double *Vp = q.V + (long long)p * q.nmax * n2;
     const double l = q.diag[(long long)p * q.nmax + k];
@@ -110,21 +169,28 @@ __global__ __launch_bounds__(256) void k_quad_update(QuadState q, int sel, int k
     q.e[ij] -= v * q.z[(long long)p * q.nmax + k];
 }
 
-// optimal weights: L^T w = z by back substitution, L[k][i] = v_{node k}[i]
-// (i < k) and L[k][k] = diag[k]; one thread per problem
+// optimal weights: L^T w = z by back substitution, L[i][k] = v_{node i}[k]
+// (the k-th column at node i, i > k) and L[k][k] = diag[k]; one wave per
+// problem, the sum over i spread over the lanes (fixed-order reduction)
+constexpr int kQuadMaxNodes = 1024;
 __global__ __launch_bounds__(64) void k_quad_weights(QuadState q, const int *nodes, int n, double *w)
 {
-    const int p = blockIdx.x * 64 + threadIdx.x;
-    if (p >= q.P) return;
+    __shared__ double ws[kQuadMaxNodes];
+    const int p = blockIdx.x, lane = threadIdx.x;
     const long long n2 = (long long)q.ntot;
     const double *Vp = q.V + (long long)p * q.nmax * n2;
-    double *wp = w + (long long)p * n;
     for (int k = n - 1; k >= 0; k--) {
-        double s = q.z[(long long)p * q.nmax + k];
-        for (int i = k + 1; i < n; i++) s -= Vp[(long long)k * n2 + nodes[i]] * wp[i];
-        const double l = q.diag[(long long)p * q.nmax + k];
-        wp[k] = l > 0.0 ? s / l : 0.0;
+        double s = 0.0;
+        for (int i = k + 1 + lane; i < n; i += 64) s += Vp[(long long)k * n2 + nodes[i]] * ws[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) {
+            const double l = q.diag[(long long)p * q.nmax + k];
+            ws[k] = l > 0.0 ? (q.z[(long long)p * q.nmax + k] - s) / l : 0.0;
+        }
+        __syncthreads();
     }
+    for (int k = lane; k < n; k += 64) w[(long long)p * n + k] = ws[k];
 }
 
 unsigned blocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -144,16 +210,30 @@ hipError_t quad_gain(const QuadState &q, const unsigned char *chosen, hipStream_
     return hipGetLastError();
 }
 
-hipError_t quad_step(const QuadState &q, int sel, int k, hipStream_t s)
+hipError_t quad_total(const QuadState &q, double *E, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, sel, k);
-    hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q, sel, k);
+    hipLaunchKernelGGL(k_quad_total, dim3(1), dim3(256), 0, s, q, E);
+    return hipGetLastError();
+}
+
+hipError_t quad_select(const QuadState &q, unsigned char *chosen, int *sels, double *err, double *E,
+                       int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_select, dim3(1), dim3(256), 0, s, q, chosen, sels, err, E, k);
+    return hipGetLastError();
+}
+
+hipError_t quad_step(const QuadState &q, const int *sels, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, sels, k);
+    hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q, sels, k);
     return hipGetLastError();
 }
 
 hipError_t quad_weights(const QuadState &q, const int *nodes_dev, int n, double *w, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_quad_weights, dim3(blocks(q.P, 64)), dim3(64), 0, s, q, nodes_dev, n, w);
+    if (n > kQuadMaxNodes) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_quad_weights, dim3(q.P), dim3(64), 0, s, q, nodes_dev, n, w);
     return hipGetLastError();
 }
 
