@@ -16,6 +16,13 @@
  *       X = alpha (T) or beta (E)                      Eq. phi2alm_r as a
  *       quadrature sum, with a = a_L + f_NL a_NL (Sect. 2).
  *
+ * Besides that forward pass it offers the reverse pass (sim_backward), the
+ * same passes with the noise regenerated from a seed instead of stored
+ * (sim_noise, sim_forward_seeded, sim_backward_seeded; Sect. 3's memory
+ * remark), grouped launches over uneven problems (sim_batch_*), and the
+ * greedy design of the radial quadrature nodes and weights
+ * (sim_quadrature_design; Sect. 3).
+ *
  * Conventions
  *   - lmax = L, nshell = N, n_lm = (L+1)(L+2)/2.
  *   - Coefficient index idx(l, m) = l(l+1)/2 + m, 0 <= m <= l <= L.  Complex
