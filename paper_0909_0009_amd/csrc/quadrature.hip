@@ -159,8 +159,17 @@ __global__ __launch_bounds__(256) void k_quad_update(QuadState q, const int *sel
     const double l = q.diag[(long long)p * q.nmax + k];
     double v = 0.0;
     if (l > 0.0) {
-        double dot = 0.0;
-        for (int i = 0; i < k; i++) dot += Vp[i * n2 + j] * Vp[i * n2 + sel];
+        // four independent partial sums keep four column loads in flight
+        double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+        int i = 0;
+        for (; i + 4 <= k; i += 4) {
+            d0 += Vp[i * n2 + j] * Vp[i * n2 + sel];
+            d1 += Vp[(i + 1) * n2 + j] * Vp[(i + 1) * n2 + sel];
+            d2 += Vp[(i + 2) * n2 + j] * Vp[(i + 2) * n2 + sel];
+            d3 += Vp[(i + 3) * n2 + j] * Vp[(i + 3) * n2 + sel];
+        }
+        for (; i < k; i++) d0 += Vp[i * n2 + j] * Vp[i * n2 + sel];
+        const double dot = (d0 + d1) + (d2 + d3);
         v = (q.C[(long long)p * n2 * n2 + (long long)sel * n2 + j] - dot) / l;
     }
     q.V[(long long)p * q.nmax * n2 + (long long)k * n2 + j] = v;
