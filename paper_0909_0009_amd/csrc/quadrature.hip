@@ -27,9 +27,17 @@ __global__ __launch_bounds__(256) void k_quad_init(QuadState q)
     if (j >= q.ntot) return;
     const double *Cp = q.C + (long long)p * q.ntot * q.ntot;
     const double *ap = q.a + (long long)p * q.ntot;
-    double b = 0.0;
-    for (int k = 0; k < q.ntot; k++) b += Cp[(long long)k * q.ntot + j] * ap[k];
-    q.e[(long long)p * q.ntot + j] = b;
+    // four independent partial sums keep four row loads in flight
+    double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
+    int k = 0;
+    for (; k + 4 <= q.ntot; k += 4) {
+        b0 += Cp[(long long)k * q.ntot + j] * ap[k];
+        b1 += Cp[(long long)(k + 1) * q.ntot + j] * ap[k + 1];
+        b2 += Cp[(long long)(k + 2) * q.ntot + j] * ap[k + 2];
+        b3 += Cp[(long long)(k + 3) * q.ntot + j] * ap[k + 3];
+    }
+    for (; k < q.ntot; k++) b0 += Cp[(long long)k * q.ntot + j] * ap[k];
+    q.e[(long long)p * q.ntot + j] = (b0 + b1) + (b2 + b3);
     q.d[(long long)p * q.ntot + j] = Cp[(long long)j * q.ntot + j];
 }
 

@@ -94,3 +94,29 @@ def test_bad_arguments(fs):
         fs.quadrature_design(cov, a, 0)
     with pytest.raises(TypeError):
         fs.quadrature_design(cov.float(), a, 2)
+
+
+def test_degenerate_problems(fs):
+    """The smallest problem (one problem, one shell, one node), and a fine grid
+    whose last shell duplicates the first: once one copy is chosen the other
+    has no conditional variance left and gains nothing, so the design never
+    picks it; errors stay finite and non-increasing, weights finite."""
+    import torch
+    cov = torch.full((1, 1, 1), 2.0, dtype=torch.float64, device="cuda")
+    a = torch.full((1, 1), 3.0, dtype=torch.float64, device="cuda")
+    nodes, err, w = fs.quadrature_design(cov, a, 1)
+    assert nodes.tolist() == [0] and abs(err[0]) <= 1e-12 * 18.0
+    assert abs(float(w[0, 0]) - 3.0) <= 1e-12
+    rng = np.random.default_rng(12)
+    n0 = 20
+    B = rng.standard_normal((n0, n0))
+    C0 = B @ B.T / n0 + 0.1 * np.eye(n0)
+    idx = list(range(n0)) + [0]                      # shell n0 repeats shell 0
+    C = C0[np.ix_(idx, idx)]
+    x = rng.standard_normal(n0 + 1)
+    nodes, err, w = fs.quadrature_design(torch.from_numpy(C[None]).cuda(),
+                                         torch.from_numpy(x[None]).cuda(), 8)
+    assert len(set(nodes.tolist())) == 8
+    assert not ({0, n0} <= set(nodes.tolist()))
+    assert np.all(np.isfinite(err)) and np.all(np.diff(err) <= 1e-12 * abs(err[0]))
+    assert np.all(np.isfinite(w.cpu().numpy()))
