@@ -186,11 +186,15 @@ int sim_backward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, co
  *   w       device [P][n] FP64 out: optimal weights of the n nodes, in the
  *           order of `nodes`
  *   stream  HIP stream (NULL = default)
+ * A shell whose variance conditional on a problem's nodes so far is at most
+ * 1e-10 of its own variance C_jj is dependent in that problem: it gains
+ * nothing there and, if chosen for the other problems, gets weight 0 in it.
+ * err[k] is sum_p (a^T C a - |z_p|^2) after step k, with z_p the Cholesky
+ * right-hand side of problem p's independent nodes.
  * Synchronous.  SIM_EINVAL for a null pointer or sizes out of range (nothing
  * launched), SIM_ENOMEM if the workspace (8 P n ntot bytes and a little more)
  * cannot be allocated, SIM_EDEVICE if a HIP call fails; the message is in
- * sim_last_error(NULL).  A shell whose conditional variance has vanished in a
- * problem contributes nothing there and gets weight 0 in that problem. */
+ * sim_last_error(NULL). */
 int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
                           int *nodes, double *err, double *w, void *stream);
 

@@ -60,11 +60,16 @@ def expected_error_eigen(C, a, nodes, w):
 
 
 def optimal_weights(C, a, nodes):
-    """Solve C_SS w = (C a)_S (the condition dE/dw_i = 0)."""
+    """Solve C_SS w = (C a)_S (the condition dE/dw_i = 0) by a symmetric
+    eigendecomposition of C_SS: eigenvalues at or below 1e-14 of the largest
+    are left out (a least-squares solution), so a set whose covariance is
+    singular up to rounding still gives finite weights."""
     C = np.asarray(C, dtype=np.float64)
     S = np.asarray(nodes, dtype=np.int64)
     rhs = (C @ np.asarray(a, dtype=np.float64))[S]
-    return np.linalg.solve(C[np.ix_(S, S)], rhs)
+    lam, U = np.linalg.eigh(C[np.ix_(S, S)])
+    keep = lam > 1e-14 * max(float(lam.max()), 0.0)
+    return U[:, keep] @ ((U[:, keep].T @ rhs) / lam[keep])
 
 
 def optimal_error(C, a, nodes):
@@ -78,22 +83,86 @@ def optimal_error(C, a, nodes):
     return float(a @ C @ a - w @ C[np.ix_(S, S)] @ w)
 
 
+# A shell whose variance conditional on the nodes already chosen is at most
+# DEPENDENT_TOL times its own variance C_jj carries no information the set
+# does not already hold (on a fine grid spaced well below the correlation
+# length this happens after a few dozen nodes): it adds nothing to that
+# problem, and its weight there is 0.
+DEPENDENT_TOL = 1e-10
+
+
+def conditional_variance(C, basis, j):
+    """d_j = C_jj - C_jB C_BB^{-1} C_Bj for the shells B already in use."""
+    C = np.asarray(C, dtype=np.float64)
+    if len(basis) == 0:
+        return float(C[j, j])
+    B = np.asarray(basis, dtype=np.int64)
+    c = C[B, j]
+    return float(C[j, j] - c @ np.linalg.solve(C[np.ix_(B, B)], c))
+
+
+def effective_sets(problems, nodes):
+    """Replay a node order: for each problem, the nodes that were not
+    dependent (conditional variance above DEPENDENT_TOL C_jj) when added."""
+    out = []
+    for C, _ in problems:
+        B = []
+        for j in nodes:
+            if conditional_variance(C, B, j) > DEPENDENT_TOL * float(np.asarray(C)[j, j]):
+                B.append(int(j))
+        out.append(B)
+    return out
+
+
+def design_errors(problems, nodes):
+    """Summed optimal error after each step of a given node order, each
+    problem using only its effective nodes (recomputed from scratch at every
+    step with the eigendecomposition solve)."""
+    errs = []
+    for k in range(1, len(nodes) + 1):
+        sets = effective_sets(problems, nodes[:k])
+        errs.append(sum(optimal_error(C, a, B) for (C, a), B in zip(problems, sets)))
+    return errs
+
+
+def design_weights(problems, nodes):
+    """[P][n] optimal weights of a node order: each problem's weights solve its
+    effective set's system; dependent nodes get weight 0."""
+    sets = effective_sets(problems, nodes)
+    W = np.zeros((len(problems), len(nodes)))
+    for p, ((C, a), B) in enumerate(zip(problems, sets)):
+        if B:
+            wB = optimal_weights(C, a, B)
+            for w, j in zip(wB, B):
+                W[p, list(nodes).index(j)] = w
+    return W
+
+
 def greedy_nodes(problems, n):
     """Greedy node design.  problems: list of (C, a) pairs on one fine grid
     (one per multipole and transfer table; T and E enter with equal weight).
     Returns (nodes in the order chosen, total optimal error after each
-    step).  Each step tries every fine shell not yet chosen."""
+    step).  Each step tries every fine shell not yet chosen and keeps the
+    one whose addition leaves the smallest summed error (the lowest index
+    among equal ones); in a problem where the shell is dependent on that
+    problem's nodes (see DEPENDENT_TOL) it changes nothing."""
     ntot = np.asarray(problems[0][0]).shape[0]
     chosen, errors = [], []
+    basis = [[] for _ in problems]
     for _ in range(n):
         best, best_err = -1, np.inf
         for j in range(ntot):
             if j in chosen:
                 continue
-            trial = chosen + [j]
-            err = sum(optimal_error(C, a, trial) for C, a in problems)
+            err = 0.0
+            for (C, a), B in zip(problems, basis):
+                indep = conditional_variance(C, B, j) > DEPENDENT_TOL * float(np.asarray(C)[j, j])
+                err += optimal_error(C, a, B + [j] if indep else B)
             if err < best_err:
                 best, best_err = j, err
         chosen.append(best)
         errors.append(best_err)
+        for p, (C, a) in enumerate(problems):
+            if conditional_variance(C, basis[p], best) > DEPENDENT_TOL * float(np.asarray(C)[best, best]):
+                basis[p].append(best)
     return chosen, errors

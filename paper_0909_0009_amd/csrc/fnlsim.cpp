@@ -1117,71 +1117,27 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
     if (P < 1 || P > 65535) return fail(nullptr, SIM_EINVAL, "P = %d outside [1, 65535]", P);
     if (ntot < 1 || ntot > 16384)
         return fail(nullptr, SIM_EINVAL, "ntot = %d outside [1, 16384]", ntot);
-    if (n < 1 || n > ntot || n > 1024)
-        return fail(nullptr, SIM_EINVAL, "n = %d outside [1, min(ntot, 1024)]", n);
+    if (n < 1 || n > ntot || n > fnl::kQuadMaxNodes)
+        return fail(nullptr, SIM_EINVAL, "n = %d outside [1, min(ntot, %d)]", n, fnl::kQuadMaxNodes);
     hipStream_t s = (hipStream_t)stream;
-    const size_t pn = (size_t)P * ntot;
-    // e, d, V, piv, z, diag, gain, aCa, then the error curve and the running error
-    const size_t nd = 2 * pn + (size_t)P * n * ntot + 2 * (size_t)P + 2 * (size_t)P * n + ntot + P +
-                      (size_t)n + 1;
-    double *ws = nullptr;
-    unsigned char *chosen = nullptr;
-    int *nodes_dev = nullptr;
-    int rc = SIM_OK;
+    const size_t ws_bytes = fnl::quad_workspace_bytes(P, ntot, n);
+    // the workspace, then the device copies of the node list and error curve
+    const size_t out_off = ws_bytes;
+    const size_t bytes = out_off + 256 + sizeof(double) * (size_t)n + sizeof(int) * (size_t)n;
+    unsigned char *ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess)
+        return fail(nullptr, SIM_ENOMEM, "workspace allocation failed (%zu bytes)", bytes);
+    double *err_dev = (double *)(ws + out_off);
+    int *nodes_dev = (int *)(err_dev + n);
     fnl::QuadState q{};
-    double *err_dev = nullptr, *E_dev = nullptr;
-    auto release = [&]() {
-        if (ws) (void)hipFree(ws);
-        if (chosen) (void)hipFree(chosen);
-        if (nodes_dev) (void)hipFree(nodes_dev);
-    };
-#define QCHECK(call)                                                                           \
-    do {                                                                                       \
-        hipError_t e_ = (call);                                                                \
-        if (e_ != hipSuccess) {                                                                \
-            rc = fail(nullptr, SIM_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));    \
-            goto done;                                                                         \
-        }                                                                                      \
-    } while (0)
-    if (hipMalloc(&ws, nd * sizeof(double)) != hipSuccess ||
-        hipMalloc(&chosen, (size_t)ntot) != hipSuccess ||
-        hipMalloc(&nodes_dev, sizeof(int) * (size_t)n) != hipSuccess) {
-        release();
-        return fail(nullptr, SIM_ENOMEM, "workspace allocation failed (%zu bytes)",
-                    nd * sizeof(double));
-    }
-    q.P = P;
-    q.ntot = ntot;
-    q.nmax = n;
-    q.C = cov;
-    q.a = a;
-    q.e = ws;
-    q.d = q.e + pn;
-    q.V = q.d + pn;
-    q.piv = q.V + (size_t)P * n * ntot;
-    q.z = q.piv + 2 * (size_t)P;
-    q.diag = q.z + (size_t)P * n;
-    q.gain = q.diag + (size_t)P * n;
-    q.aCa = q.gain + ntot;
-    err_dev = q.aCa + P;
-    E_dev = err_dev + n;
-    QCHECK(hipMemsetAsync(chosen, 0, (size_t)ntot, s));
-    QCHECK(fnl::quad_init(q, s));
-    QCHECK(fnl::quad_total(q, E_dev, s));
-    // every step runs on the device: gains, the choice (largest gain among
-    // the shells not yet chosen, lowest index on ties), the Cholesky column
-    for (int k = 0; k < n; k++) {
-        QCHECK(fnl::quad_gain(q, chosen, s));
-        QCHECK(fnl::quad_select(q, chosen, nodes_dev, err_dev, E_dev, k, s));
-        QCHECK(fnl::quad_step(q, nodes_dev, k, s));
-    }
-    QCHECK(fnl::quad_weights(q, nodes_dev, n, w, s));
-    QCHECK(hipMemcpyAsync(nodes, nodes_dev, sizeof(int) * n, hipMemcpyDeviceToHost, s));
-    QCHECK(hipMemcpyAsync(err, err_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s));
-    QCHECK(hipStreamSynchronize(s));
-done:
-#undef QCHECK
-    release();
+    fnl::quad_bind(q, P, ntot, n, cov, a, ws);
+    int rc = SIM_OK;
+    hipError_t e = fnl::quad_run(q, n, nodes_dev, err_dev, w, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(nodes, nodes_dev, sizeof(int) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(err, err_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) rc = fail(nullptr, SIM_EDEVICE, "quadrature design: %s", hipGetErrorString(e));
+    (void)hipFree(ws);
     return rc;
 }
 

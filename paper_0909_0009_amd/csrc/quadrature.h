@@ -4,34 +4,47 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 namespace fnl {
+
+// A shell whose conditional variance d_j has fallen to kQuadDependent C_jj or
+// below is dependent on the nodes already chosen in that problem: it adds no
+// gain there, and if chosen it gets a zero Cholesky pivot (weight 0).
+constexpr double kQuadDependent = 1e-10;
+// Problems per partial gain sum (the gain of a shell is summed over problems
+// in chunks of this many, then the chunks in order).
+constexpr int kQuadPChunk = 32;
+constexpr int kQuadMaxNodes = 1024;
 
 // Problem sizes and device state of one design run.  Arrays (device, FP64):
 //   C [P][ntot][ntot]  covariance of Phi on the fine grid, per problem
 //   a [P][ntot]        fine-sum weights
 //   e [P][ntot]        residual numerator b_j - v_j . z   (b = C a)
 //   d [P][ntot]        conditional variance C_jj - |v_j|^2
+//   cdiag [P][ntot]    C_jj (the scale of the dependence test)
 //   V [P][nmax][ntot]  column k: the k-th Cholesky column of the chosen set,
 //                      v_j[k] for every shell j
-//   piv [P][2]         (d, e) of the node chosen at the current step
 //   z [P][nmax], diag [P][nmax]   Cholesky right-hand side and diagonal
-//   gain [ntot]        sum_p e_pj^2 / d_pj
+//   zz [P]             |z|^2 so far: the error of problem p is a^T C a - zz
+//   gpart [npc][ntot]  partial gains, sum over one chunk of problems of e^2 / d
 //   aCa [P]            a^T C a per problem
+//   chosen [ntot]      1 once a shell is a node (bytes)
 struct QuadState {
-    int P, ntot, nmax;
+    int P, ntot, nmax, npc;
     const double *C, *a;
-    double *e, *d, *V, *piv, *z, *diag, *gain, *aCa;
+    double *e, *d, *cdiag, *V, *z, *diag, *zz, *gpart, *aCa;
+    unsigned char *chosen;
 };
 
-hipError_t quad_init(const QuadState &q, hipStream_t s);
-// *E = sum_p a^T C a
-hipError_t quad_total(const QuadState &q, double *E, hipStream_t s);
-hipError_t quad_gain(const QuadState &q, const unsigned char *chosen, hipStream_t s);
-// step k: sels[k] = best unchosen shell (lowest index on ties), chosen[sels[k]] = 1,
-// *E -= its gain, err[k] = *E (all device memory)
-hipError_t quad_select(const QuadState &q, unsigned char *chosen, int *sels, double *err, double *E,
-                       int k, hipStream_t s);
-hipError_t quad_step(const QuadState &q, const int *sels, int k, hipStream_t s);
-hipError_t quad_weights(const QuadState &q, const int *nodes_dev, int n, double *w, hipStream_t s);
+// Bytes of device workspace a design of these sizes needs, and the binding
+// of a QuadState's arrays to such a workspace (256-byte aligned base).
+size_t quad_workspace_bytes(int P, int ntot, int n);
+void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws);
+
+// The whole design on stream s, asynchronous: clears the workspace state it
+// needs, then n greedy steps, then the weights.  nodes [n] (int), err [n] and
+// w [P][n] are device arrays.
+hipError_t quad_run(QuadState &q, int n, int *nodes, double *err, double *w, hipStream_t s);
 
 }  // namespace fnl

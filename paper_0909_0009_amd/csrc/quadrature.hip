@@ -7,9 +7,15 @@
 // one shell j lowers it by  (b_j - v_j . z)^2 / (C_jj - |v_j|^2),  where
 // C_SS = L L^T, v_j = L^{-1} C_Sj and z = L^{-1} b_S: an incremental Cholesky
 // factorisation.  Every step sums that gain over the problems for every
-// candidate shell (one block per shell), picks the best shell on the device,
-// and forms one more column of L for every (problem, shell) at once; the
-// host only launches.
+// candidate shell, picks the best shell on the device, and forms one more
+// column of L for every (problem, shell) at once; the host only launches.
+//
+// On a fine grid spaced well below the correlation length the conditional
+// variances C_jj - |v_j|^2 collapse to rounding noise after a few dozen
+// nodes.  A shell is then treated as dependent in that problem (d_j at or
+// below kQuadDependent C_jj): it gains nothing and, if chosen for the sake of
+// other problems, gets a zero pivot there.  The error after each step is
+// a^T C a - |z|^2 per problem, summed in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include "quadrature.h"
@@ -37,11 +43,15 @@ __global__ __launch_bounds__(256) void k_quad_init(QuadState q)
         b3 += Cp[(long long)(k + 3) * q.ntot + j] * ap[k + 3];
     }
     for (; k < q.ntot; k++) b0 += Cp[(long long)k * q.ntot + j] * ap[k];
+    const double cjj = Cp[(long long)j * q.ntot + j];
     q.e[(long long)p * q.ntot + j] = (b0 + b1) + (b2 + b3);
-    q.d[(long long)p * q.ntot + j] = Cp[(long long)j * q.ntot + j];
+    q.d[(long long)p * q.ntot + j] = cjj;
+    q.cdiag[(long long)p * q.ntot + j] = cjj;
+    if (p == 0) q.chosen[j] = 0;
 }
 
-// a^T C a = a . b per problem (one block per problem, fixed summation order)
+// a^T C a = a . b per problem (one block per problem, fixed summation order);
+// |z|^2 starts at 0
 __global__ __launch_bounds__(256) void k_quad_aca(QuadState q)
 {
     __shared__ double part[256];
@@ -56,61 +66,44 @@ __global__ __launch_bounds__(256) void k_quad_aca(QuadState q)
         if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) q.aCa[p] = part[0];
+    if (threadIdx.x == 0) {
+        q.aCa[p] = part[0];
+        q.zz[p] = 0.0;
+    }
 }
 
-// gain_j = sum_p e_pj^2 / d_pj over the problems (chosen shells: 0; a shell
-// whose conditional variance has vanished in a problem adds nothing there).
-// One block per shell, threads over the problems, a fixed-order tree sum.
-__global__ __launch_bounds__(256) void k_quad_gain(QuadState q, const unsigned char *chosen)
+// Partial gains: thread (shell j, problem chunk c) sums e_pj^2 / d_pj over the
+// chunk's problems in order (adjacent threads read adjacent shells of one
+// problem row); a dependent shell adds nothing in that problem.
+__global__ __launch_bounds__(64) void k_quad_gain(QuadState q)
 {
-    __shared__ double part[256];
-    const int j = blockIdx.x;
+    const int j = blockIdx.x * 64 + threadIdx.x;
+    const int c = blockIdx.y;
+    if (j >= q.ntot) return;
+    const int p1 = min(q.P, (c + 1) * kQuadPChunk);
     double g = 0.0;
-    if (!chosen[j]) {
-        for (int p = threadIdx.x; p < q.P; p += 256) {
-            const double dj = q.d[(long long)p * q.ntot + j];
-            const double ej = q.e[(long long)p * q.ntot + j];
-            if (dj > 0.0) g += ej * ej / dj;
-        }
+    for (int p = c * kQuadPChunk; p < p1; p++) {
+        const long long pj = (long long)p * q.ntot + j;
+        const double dj = q.d[pj];
+        const double ej = q.e[pj];
+        if (dj > kQuadDependent * q.cdiag[pj]) g += ej * ej / dj;
     }
-    part[threadIdx.x] = g;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) q.gain[j] = part[0];
+    q.gpart[(long long)c * q.ntot + j] = g;
 }
 
-// E = sum_p a^T C a (one block, fixed order)
-__global__ __launch_bounds__(256) void k_quad_total(QuadState q, double *E)
-{
-    __shared__ double part[256];
-    double s = 0.0;
-    for (int p = threadIdx.x; p < q.P; p += 256) s += q.aCa[p];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) *E = part[0];
-}
-
-// step k's node: the largest gain among the shells not yet chosen, the lowest
-// index on ties (one block); records it, marks it chosen and lowers the
-// running error E by its gain
-__global__ __launch_bounds__(256) void k_quad_select(QuadState q, unsigned char *chosen, int *sel,
-                                                     double *err, double *E, int k)
+// step k's node: the largest gain (partials summed over the chunks in order)
+// among the shells not yet chosen, the lowest index on ties (one block);
+// records it and marks it chosen
+__global__ __launch_bounds__(256) void k_quad_select(QuadState q, int *sel, int k)
 {
     __shared__ double gv[256];
     __shared__ int gi[256];
     double best = 0.0;
     int bi = -1;
     for (int j = threadIdx.x; j < q.ntot; j += 256) {
-        if (chosen[j]) continue;
-        const double g = q.gain[j];
+        if (q.chosen[j]) continue;
+        double g = 0.0;
+        for (int c = 0; c < q.npc; c++) g += q.gpart[(long long)c * q.ntot + j];
         if (bi < 0 || g > best) {  // j ascending: a tie keeps the lower index
             best = g;
             bi = j;
@@ -133,25 +126,39 @@ __global__ __launch_bounds__(256) void k_quad_select(QuadState q, unsigned char 
     if (threadIdx.x == 0) {
         const int s = gi[0];  // n <= ntot: an unchosen shell always exists
         sel[k] = s;
-        chosen[s] = 1;
-        *E -= gv[0];
-        err[k] = *E;
+        q.chosen[s] = 1;
     }
 }
 
-// the chosen shell's (d, e) per problem, read before the step overwrites them
+// the chosen shell's pivot per problem: L_kk = sqrt(d_sel) (0 if dependent),
+// z_k = e_sel / L_kk, |z|^2 += z_k^2
 __global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, const int *sels, int k)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= q.P) return;
-    const int sel = sels[k];
-    const double dd = q.d[(long long)p * q.ntot + sel];
-    const double ee = q.e[(long long)p * q.ntot + sel];
-    q.piv[2 * p] = dd;
-    q.piv[2 * p + 1] = ee;
-    const double l = dd > 0.0 ? sqrt(dd) : 0.0;
+    const long long ps = (long long)p * q.ntot + sels[k];
+    const double dd = q.d[ps];
+    const double ee = q.e[ps];
+    const double l = dd > kQuadDependent * q.cdiag[ps] ? sqrt(dd) : 0.0;
+    const double zk = l > 0.0 ? ee / l : 0.0;
     q.diag[(long long)p * q.nmax + k] = l;
-    q.z[(long long)p * q.nmax + k] = l > 0.0 ? ee / l : 0.0;
+    q.z[(long long)p * q.nmax + k] = zk;
+    q.zz[p] += zk * zk;
+}
+
+// err[k] = sum_p (a^T C a - |z|^2) (one block, fixed order)
+__global__ __launch_bounds__(256) void k_quad_err(QuadState q, double *err, int k)
+{
+    __shared__ double part[256];
+    double s = 0.0;
+    for (int p = threadIdx.x; p < q.P; p += 256) s += q.aCa[p] - q.zz[p];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) err[k] = part[0];
 }
 
 // column k of L for every shell j: v_j[k] = (C_j,sel - sum_{i<k} v_j[i] v_sel[i]) / l,
@@ -189,7 +196,6 @@ __global__ __launch_bounds__(256) void k_quad_update(QuadState q, const int *sel
 // optimal weights: L^T w = z by back substitution, L[i][k] = v_{node i}[k]
 // (the k-th column at node i, i > k) and L[k][k] = diag[k]; one wave per
 // problem, the sum over i spread over the lanes (fixed-order reduction)
-constexpr int kQuadMaxNodes = 1024;
 __global__ __launch_bounds__(64) void k_quad_weights(QuadState q, const int *nodes, int n, double *w)
 {
     __shared__ double ws[kQuadMaxNodes];
@@ -212,45 +218,65 @@ __global__ __launch_bounds__(64) void k_quad_weights(QuadState q, const int *nod
 
 unsigned blocks(long long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
 }  // namespace
 
-hipError_t quad_init(const QuadState &q, hipStream_t s)
+size_t quad_workspace_bytes(int P, int ntot, int n)
 {
+    const size_t pn = (size_t)P * ntot;
+    const int npc = (P + kQuadPChunk - 1) / kQuadPChunk;
+    return align256(8 * pn) * 3                        // e, d, cdiag
+           + align256(8 * pn * (size_t)n)               // V
+           + align256(8 * (size_t)P * n) * 2            // z, diag
+           + align256(8 * (size_t)P) * 2                // zz, aCa
+           + align256(8 * (size_t)npc * ntot)           // gpart
+           + align256((size_t)ntot);                    // chosen
+}
+
+void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws)
+{
+    const size_t pn = (size_t)P * ntot;
+    q.P = P;
+    q.ntot = ntot;
+    q.nmax = n;
+    q.npc = (P + kQuadPChunk - 1) / kQuadPChunk;
+    q.C = C;
+    q.a = a;
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    auto take = [&](size_t bytes) {
+        unsigned char *p = b;
+        b += align256(bytes);
+        return p;
+    };
+    q.e = (double *)take(8 * pn);
+    q.d = (double *)take(8 * pn);
+    q.cdiag = (double *)take(8 * pn);
+    q.V = (double *)take(8 * pn * (size_t)n);
+    q.z = (double *)take(8 * (size_t)P * n);
+    q.diag = (double *)take(8 * (size_t)P * n);
+    q.zz = (double *)take(8 * (size_t)P);
+    q.aCa = (double *)take(8 * (size_t)P);
+    q.gpart = (double *)take(8 * (size_t)q.npc * ntot);
+    q.chosen = take((size_t)ntot);
+}
+
+hipError_t quad_run(QuadState &q, int n, int *nodes, double *err, double *w, hipStream_t s)
+{
+    if (n < 1 || n > kQuadMaxNodes || n > q.nmax) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_quad_init, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q);
     hipLaunchKernelGGL(k_quad_aca, dim3(q.P), dim3(256), 0, s, q);
-    return hipGetLastError();
-}
-
-hipError_t quad_gain(const QuadState &q, const unsigned char *chosen, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_quad_gain, dim3(q.ntot), dim3(256), 0, s, q, chosen);
-    return hipGetLastError();
-}
-
-hipError_t quad_total(const QuadState &q, double *E, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_quad_total, dim3(1), dim3(256), 0, s, q, E);
-    return hipGetLastError();
-}
-
-hipError_t quad_select(const QuadState &q, unsigned char *chosen, int *sels, double *err, double *E,
-                       int k, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_quad_select, dim3(1), dim3(256), 0, s, q, chosen, sels, err, E, k);
-    return hipGetLastError();
-}
-
-hipError_t quad_step(const QuadState &q, const int *sels, int k, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, sels, k);
-    hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q, sels, k);
-    return hipGetLastError();
-}
-
-hipError_t quad_weights(const QuadState &q, const int *nodes_dev, int n, double *w, hipStream_t s)
-{
-    if (n > kQuadMaxNodes) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_quad_weights, dim3(q.P), dim3(64), 0, s, q, nodes_dev, n, w);
+    // every step runs on the device: partial gains, the choice (largest gain
+    // among the shells not yet chosen, lowest index on ties), the pivot and
+    // the error, the Cholesky column
+    for (int k = 0; k < n; k++) {
+        hipLaunchKernelGGL(k_quad_gain, dim3(blocks(q.ntot, 64), q.npc), dim3(64), 0, s, q);
+        hipLaunchKernelGGL(k_quad_select, dim3(1), dim3(256), 0, s, q, nodes, k);
+        hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, nodes, k);
+        hipLaunchKernelGGL(k_quad_err, dim3(1), dim3(256), 0, s, q, err, k);
+        hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q, nodes, k);
+    }
+    hipLaunchKernelGGL(k_quad_weights, dim3(q.P), dim3(64), 0, s, q, nodes, n, w);
     return hipGetLastError();
 }
 

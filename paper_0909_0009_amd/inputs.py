@@ -224,6 +224,88 @@ def covariance(L, r, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=4096, kchunk=64,
     return C
 
 
+def _sph_bessel_table_torch(L, x):
+    """sph_bessel_table with torch FP64 tensors on the tensor's device: the
+    same upward / Miller downward recurrences, normalisation and sign rule."""
+    import torch
+    out = torch.zeros((L + 1, x.numel()), dtype=torch.float64, device=x.device)
+    up = x > L + 60.0
+    if bool(up.any()):
+        xs = x[up]
+        j0 = torch.sin(xs) / xs
+        j1 = torch.sin(xs) / xs ** 2 - torch.cos(xs) / xs
+        rows = [j0] + ([j1] if L >= 1 else [])
+        jm, jc = j0, j1
+        for l in range(1, L):
+            jn = (2 * l + 1) / xs * jc - jm
+            rows.append(jn)
+            jm, jc = jc, jn
+        out[:, up] = torch.stack(rows[:L + 1])
+    dn = ~up
+    if bool(dn.any()):
+        xs = x[dn]
+        Ls = max(L, 1)
+        xmax = float(xs.max())
+        top = max(int(min(Ls + 200, xmax + 60 + 8 * xmax ** (1 / 3))), 2)
+        t_next = torch.zeros_like(xs)
+        t_cur = torch.full_like(xs, 1e-100)
+        scale = torch.zeros(xs.numel(), dtype=torch.int64, device=x.device)
+        stored = torch.zeros((Ls + 1, xs.numel()), dtype=torch.float64, device=x.device)
+        stored_scale = torch.zeros((Ls + 1, xs.numel()), dtype=torch.int64, device=x.device)
+        norm = (2 * top + 1) * t_cur ** 2
+        for l in range(top, 0, -1):
+            t_prev = (2 * l + 1) / xs * t_cur - t_next
+            t_next, t_cur = t_cur, t_prev
+            norm = norm + (2 * l - 1) * t_cur ** 2
+            big = t_cur.abs() > 1e120
+            # rescale where needed (a no-op elsewhere; no host sync per step)
+            f = torch.where(big, 1e-120, 1.0)
+            t_cur = t_cur * f
+            t_next = t_next * f
+            norm = norm * f * f
+            scale = scale + big.to(torch.int64)
+            if l - 1 <= Ls:
+                stored[l - 1] = t_cur
+                stored_scale[l - 1] = scale
+        lag = scale[None, :] - stored_scale
+        stored = stored * torch.where(lag == 0, 1.0, torch.where(lag == 1, 1e-120, 0.0))
+        mag = 1.0 / torch.sqrt(norm)
+        j0 = torch.sin(xs) / xs
+        j1 = torch.sin(xs) / xs ** 2 - torch.cos(xs) / xs
+        use0 = j0.abs() >= j1.abs()
+        sign = torch.sign(torch.where(use0, j0 * stored[0], j1 * stored[1]))
+        sign[sign == 0] = 1.0
+        out[:, dn] = stored[:L + 1] * (mag * sign)[None, :]
+    return out
+
+
+def covariance_torch(L, r, device, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=4096, kchunk=1024):
+    """covariance() evaluated with torch FP64 on `device` (a GPU makes the
+    paper-scale tables take about a second instead of minutes): the same k
+    grid, trapezoid rule in ln k and Bessel recurrences; sums in another
+    order, so the result agrees with covariance() to rounding."""
+    import torch
+    r_np = np.asarray(r, dtype=np.float64)
+    k_np = np.geomspace(kmin, kmax, nk)
+    h = math.log(kmax / kmin) / (nk - 1)
+    dlnk = np.full(nk, h)
+    dlnk[0] = dlnk[-1] = 0.5 * h
+    D_np = (2.0 / math.pi) * A * (k_np / 0.05) ** (ns - 1.0) * dlnk
+    rt = torch.from_numpy(r_np).to(device)
+    N = r_np.size
+    C = torch.zeros((L + 1, N, N), dtype=torch.float64, device=device)
+    for q0 in range(0, nk, kchunk):
+        kc = torch.from_numpy(k_np[q0:q0 + kchunk]).to(device)
+        Dc = torch.from_numpy(D_np[q0:q0 + kchunk]).to(device)
+        J = _sph_bessel_table_torch(L, torch.outer(rt, kc).reshape(-1)).reshape(L + 1, N, kc.numel())
+        JD = (J * Dc[None, None, :]).contiguous()
+        C += torch.matmul(JD, J.transpose(1, 2).contiguous())
+        del J, JD
+    out = C.cpu().numpy()
+    del C
+    return out
+
+
 def filter_from_covariance(C, jitter=1e-12):
     """Lower-triangular F_l with F_l F_l^T = C_l + jitter * max diag(C_l) I."""
     L1, N, _ = C.shape
@@ -292,15 +374,19 @@ def _cache_dir():
     return d
 
 
-def problem(L, N, seed=TRANSFER_SEED, cache=True):
-    """dict(r, w, filter, alpha, beta, cov) for band limit L and N nodes."""
-    key = hashlib.sha1(f"v2|{L}|{N}|{seed}".encode()).hexdigest()[:16]
+def problem(L, N, seed=TRANSFER_SEED, cache=True, device=None):
+    """dict(r, w, filter, alpha, beta, cov) for band limit L and N nodes.
+    device: None evaluates the covariance with numpy on the host; a torch
+    device (e.g. "cuda") evaluates it there (covariance_torch); the two agree
+    to rounding and are cached apart."""
+    tag = "v2" if device is None else "v2t"
+    key = hashlib.sha1(f"{tag}|{L}|{N}|{seed}".encode()).hexdigest()[:16]
     path = os.path.join(_cache_dir(), f"problem_L{L}_N{N}_{key}.npz") if cache else None
     if path and os.path.exists(path):
         with np.load(path, allow_pickle=False) as z:
             return {k: z[k] for k in z.files}
     r, w = radial_nodes(N)
-    C = covariance(L, r)
+    C = covariance(L, r) if device is None else covariance_torch(L, r, device)
     F = filter_from_covariance(C)
     alpha, beta = transfer_tables(L, r, seed)
     out = dict(r=r, w=w, filter=F, alpha=alpha, beta=beta, cov=C)

@@ -1,0 +1,151 @@
+"""Batching form against the FP64 oracle: the uneven 32-realization workload
+(lmax drawn from {128, 256, 512, 1024}, 64..200 nodes, default_rng(33), f_NL =
+50, FP32 matrix-core path) through sim_batch_forward, every realization
+compared with the oracle at the FP32 bar.  The transfer tables of each
+context are zeroed except on one node per column tile of its Legendre
+kernels (the oracle then evaluates only those shells; the linear part still
+sums the filter over every node), so every column tile of every context is
+checked.  A second, small mix reaches the grouped ring kernels' run-time FFT
+plans at ring lengths 1800 and 3375 in both precisions."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_0909_0009_amd import inputs
+from tests.parity import assert_close
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def fs():
+    import os
+
+    import torch
+    from paper_0909_0009_amd import build, fnlsim
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    if not os.path.exists(fnlsim.LIB_PATH):
+        build.build()
+    fnlsim.lib()
+    return fnlsim
+
+
+def _col_tile(N):
+    """The default column tile: 16 CF columns, CF in 5..1 giving the least
+    padding of the 2N real columns (the first such CF from 5 down)."""
+    best, pad = 0, None
+    for cf in range(5, 0, -1):
+        ct = 16 * cf
+        pd = -(-2 * N // ct) * ct - 2 * N
+        if pad is None or pd < pad:
+            best, pad = ct, pd
+    return best
+
+
+def _keep(N, col_tile):
+    """One node per column tile (tile t holds shells [t CT/2, (t+1) CT/2)):
+    the middle of each full tile and the last node."""
+    half = col_tile // 2
+    keep = [min(N - 1, t * half + half // 2) for t in range((N + half - 1) // half)]
+    return sorted(set(keep + [N - 1]))
+
+
+def _sampled(p, keep):
+    al = np.zeros_like(p["alpha"])
+    be = np.zeros_like(p["beta"])
+    al[:, keep] = p["alpha"][:, keep]
+    be[:, keep] = p["beta"][:, keep]
+    return al, be
+
+
+def _run_batch(fs, sims, noises, fnls):
+    import torch
+    outs = [(torch.empty((1, s.n_lm), dtype=torch.complex128, device="cuda"),
+             torch.empty((1, s.n_lm), dtype=torch.complex128, device="cuda")) for s in sims]
+    b = fs.Batch(sims)
+    try:
+        b.forward(noises, fnls, outs)
+        torch.cuda.synchronize()
+        # a graph replay with the same inputs gives the same result
+        again = [(torch.empty_like(o[0]), torch.empty_like(o[1])) for o in outs]
+        b.forward(noises, fnls, again)
+        torch.cuda.synchronize()
+        assert all(torch.equal(o[0], a[0]) and torch.equal(o[1], a[1]) for o, a in zip(outs, again))
+    finally:
+        b.close()
+    return outs
+
+
+@pytest.fixture(scope="module")
+def c3(fs):
+    """Build the 32 contexts, run the batch once, keep what the checks need."""
+    import time
+
+    import torch
+    mix = inputs.batch_mix()
+    t0 = time.time()
+    sims, noises, metas = [], [], []
+    for i, (L, N) in enumerate(mix):
+        p = inputs.problem(L, N, device="cuda")
+        keep = _keep(N, _col_tile(N))
+        al, be = _sampled(p, keep)
+        sim = fs.Simulator(L, p["r"], p["w"], p["filter"], al, be, precision="fp32")
+        assert sim.col_tile == _col_tile(N)
+        noise = inputs.noise(L, N, inputs.realization_seed(i)).astype(np.complex64)
+        sims.append(sim)
+        noises.append(torch.from_numpy(noise).cuda())
+        metas.append((L, N, keep, p, al, be))
+    print(f"batch inputs ready in {time.time() - t0:.1f} s", flush=True)
+    outs = _run_batch(fs, sims, noises, [50.0] * len(mix))
+    res = [(o[0].cpu().numpy().ravel(), o[1].cpu().numpy().ravel()) for o in outs]
+    for s in sims:
+        s.close()
+    return metas, res, [n.cpu().numpy() for n in noises]
+
+
+@pytest.mark.parametrize("i", range(32))
+def test_batch_realization_matches_oracle(orc, c3, i):
+    metas, res, noises = c3
+    L, N, keep, p, al, be = metas[i]
+    noise = noises[i].astype(np.complex128)
+    ref = orc.Problem(L, p["r"], p["w"], p["filter"], al, be).forward(noise, 50.0)
+    eT = assert_close(res[i][0], ref["aT"], L, TOL["fp32"], f"batch r={i} L={L} N={N} aT")
+    eE = assert_close(res[i][1], ref["aE"], L, TOL["fp32"], f"batch r={i} L={L} N={N} aE")
+    print(f"r={i} L={L} N={N} shells {keep}: aT {eT:.2e} aE {eE:.2e}", flush=True)
+
+
+# lmax 600: n_phi = 1800 (run-time plan, 2048-point bucket, alias term);
+# lmax 1100: 3L = 3300 is not 5-smooth, n_phi = 3375 (run-time plan,
+# 4096-point bucket, no alias); lmax 40: 120 points (1024 bucket)
+SMALL_MIX = [(600, 5), (1100, 3), (40, 9)]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_batch_runtime_fft_plans_match_oracle(fs, orc, precision):
+    import torch
+    dt = np.complex128 if precision == "fp64" else np.complex64
+    sims, noises, probs = [], [], []
+    for k, (L, N) in enumerate(SMALL_MIX):
+        p = inputs.problem(L, N, device="cuda")
+        probs.append(p)
+        sims.append(fs.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                                 precision=precision))
+        noises.append(torch.from_numpy(inputs.noise(L, N, 700 + k).astype(dt)).cuda())
+    assert [s.n_phi for s in sims] == [1800, 3375, 120]
+    fnls = [30.0, -60.0, 90.0]
+    outs = _run_batch(fs, sims, noises, fnls)
+    for k, (L, N) in enumerate(SMALL_MIX):
+        p = probs[k]
+        ref = orc.Problem(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"]).forward(
+            noises[k].cpu().numpy().astype(np.complex128), fnls[k])
+        eT = assert_close(outs[k][0].cpu().numpy().ravel(), ref["aT"], L, TOL[precision],
+                          f"{precision} L={L} aT")
+        eE = assert_close(outs[k][1].cpu().numpy().ravel(), ref["aE"], L, TOL[precision],
+                          f"{precision} L={L} aE")
+        print(f"{precision} L={L} N={N} n_phi={sims[k].n_phi}: aT {eT:.2e} aE {eE:.2e}", flush=True)
+    for s in sims:
+        s.close()

@@ -38,6 +38,20 @@ def _per_l_all_shells(g, ref, L):
     return float(np.max(num / den))
 
 
+def _per_shell_errors(g, ref, L):
+    """Per input shell j: max over l of ||g_j - ref_j||_l / ||ref_j||_l, and the
+    same error measured against the largest shell's norm at that l."""
+    ls, ms = inputs.lm_arrays(L)
+    c = np.where(ms == 0, 1.0, 2.0)
+    num = np.stack([np.sqrt(np.bincount(ls, weights=c * np.abs(g[j] - ref[j]) ** 2, minlength=L + 1))
+                    for j in range(ref.shape[0])])
+    den = np.stack([np.sqrt(np.bincount(ls, weights=c * np.abs(ref[j]) ** 2, minlength=L + 1))
+                    for j in range(ref.shape[0])])
+    top = np.maximum(den.max(axis=0), 1e-300)
+    rel = np.where(den > 0, num / np.where(den > 0, den, 1.0), np.where(num > 0, np.inf, 0.0))
+    return rel.max(axis=1), (num / top[None, :]).max(axis=1), den.max(axis=1) / top.max()
+
+
 def _compare_grad(gn, ref_gn, gf, ref_gf, L, tol, tag):
     worst = 0.0
     if tol < 1e-8:
@@ -47,10 +61,18 @@ def _compare_grad(gn, ref_gn, gf, ref_gf, L, tol, tag):
                 continue
             worst = max(worst, assert_close(gn[i], ref_gn[i], L, tol, f"{tag} grad shell {i}"))
     else:
-        # FP32: per l over the whole gradient.  Single shells can lose digits to
-        # cancellation between F_ij Phibar_i terms of nearby nodes (FP32 F).
-        worst = _per_l_all_shells(gn, ref_gn, L)
-        assert worst <= tol, f"{tag} grad per-l error {worst:.3e} > {tol}"
+        # FP32: every input shell separately (per-l relative rms of that
+        # shell's own gradient), with the aggregate over all shells and the
+        # error against the largest shell's gradient reported beside it
+        agg = _per_l_all_shells(gn, ref_gn, L)
+        rel, vs_top, size = _per_shell_errors(gn, ref_gn, L)
+        order = np.argsort(rel)[::-1][:4]
+        print(tag, f"aggregate {agg:.1e}; worst shells (shell, own-norm error, error vs "
+              "largest shell, norm vs largest):",
+              [(int(j), f"{rel[j]:.1e}", f"{vs_top[j]:.1e}", f"{size[j]:.1e}") for j in order],
+              flush=True)
+        worst = float(np.max(rel))
+        assert worst <= tol, f"{tag} grad of shell {int(np.argmax(rel))}: {worst:.3e} > {tol}"
     rel = abs(gf - ref_gf) / max(abs(ref_gf), 1e-300)
     assert rel <= tol, f"{tag} grad_fnl {gf} vs {ref_gf} ({rel:.2e})"
     print(tag, f"grad_n {worst:.2e} grad_fnl {rel:.2e}", flush=True)
@@ -149,13 +171,13 @@ def test_autograd_function(fs):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_grad_workload_sampled_shells(fs, orc, precision):
     """lmax 512, 96 nodes, 769 x 1536 grid (the differentiation workload), with
-    the transfer tables zeroed except on two nodes so the CPU adjoint stays
-    cheap; loss as in the workload with a target from a second seed."""
+    the transfer tables zeroed except on one node per column tile so the
+    CPU adjoint stays cheap; loss as in the workload with a target from a second seed."""
     import torch
     cfg = inputs.CONFIGS["grad"]
     L, N, fnl = cfg["lmax"], cfg["nshell"], cfg["fnl"]
     p = inputs.problem(L, N)
-    keep = [N // 2 - 3, N // 2 + 5]
+    keep = [3, 45, 92]   # one node in each of the three 64-column tiles
     al = np.zeros_like(p["alpha"])
     be = np.zeros_like(p["beta"])
     al[:, keep] = p["alpha"][:, keep]

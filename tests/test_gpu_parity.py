@@ -140,27 +140,39 @@ def test_edge_shapes_fp64(fs, orc, L, N, nring, nphi, mean, R):
         _check_all([g[k] for g in got], ref, L, TOL["fp64"], f"edge L={L} N={N} r={k}")
 
 
+# Paper workload: 200 nodes = 400 real columns in five 80-column tiles of the
+# Legendre kernels (40 shells each); one kept shell per tile, the last one
+# included.
+PAPER_KEEP = [0, 45, 93, 140, 199]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_paper_scale_sampled_shells(fs, orc, precision):
     """Full lmax = 1024, 200 nodes, 1537 x 3072 grid in the benchmark's launch
-    configuration; the transfer tables are zeroed except on two nodes so the
-    oracle only has to evaluate those two shells."""
+    configuration, at f_NL = 0 and 100; the transfer tables are zeroed except
+    on one node of every column tile, so the oracle only has to evaluate
+    those shells (the linear part still sums the filter over all nodes)."""
     cfg = inputs.CONFIGS["paper"]
     L, N = cfg["lmax"], cfg["nshell"]
     p = _problem(L, N)
-    keep = [N // 2 - 7, N // 2 + 3]
+    keep = PAPER_KEEP
     al = np.zeros_like(p["alpha"])
     be = np.zeros_like(p["beta"])
     al[:, keep] = p["alpha"][:, keep]
     be[:, keep] = p["beta"][:, keep]
     sim = fs.Simulator(L, p["r"], p["w"], p["filter"], al, be, precision=precision,
                        n_ring=cfg["ntheta"], n_phi=cfg["nphi"])
+    assert sim.col_tile == 80 and sorted({2 * s // 80 for s in keep}) == [0, 1, 2, 3, 4]
     noise = inputs.noise(L, N, inputs.realization_seed(0))
     if precision == "fp32":
         noise = noise.astype(np.complex64).astype(np.complex128)
-    got = sim.forward(_dev(noise, precision), cfg["fnl"], want_nl=True)
     ref = _oracle(orc, p, L, alpha=al, beta=be).forward(noise, cfg["fnl"])
-    _check_all(got, ref, L, TOL[precision], f"paper {precision}")
+    dev = _dev(noise, precision)
+    got = sim.forward(dev, cfg["fnl"], want_nl=True)
+    _check_all(got, ref, L, TOL[precision], f"paper {precision} f_NL={cfg['fnl']}")
+    got0 = sim.forward(dev, 0.0, want_nl=True)
+    ref0 = dict(ref, aT=ref["aT_lin"], aE=ref["aE_lin"])
+    _check_all(got0, ref0, L, TOL[precision], f"paper {precision} f_NL=0")
 
 
 def test_many_shells_fp32(fs, orc):

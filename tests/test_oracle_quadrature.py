@@ -98,3 +98,59 @@ def test_design_on_the_synthetic_inputs():
     err_even = sum(q.optimal_error(Cl, a, even) for Cl, a in rel)
     assert abs(r[nodes[0]] - 14000.0) < 100.0
     assert errs[-1] < 0.1 * err_even
+
+
+def _tight_problems(L=4, ntot=120, spacing=2.0):
+    """T and E problems for l = 2..L on a fine grid spaced `spacing` Mpc
+    around 14000 Mpc (far below the correlation length), each scaled to unit
+    a^T C a."""
+    r = 14000.0 + spacing * (np.arange(ntot) - ntot // 2)
+    C = inputs.covariance(L, r)
+    alpha, beta = inputs.transfer_tables(L, r)
+    probs = []
+    for l in range(2, L + 1):
+        for X in (alpha, beta):
+            a = q.fine_weights(r, X[l])
+            probs.append((C[l] / float(a @ C[l] @ a), a))
+    return probs
+
+
+def test_design_on_a_tight_grid_stays_nonnegative():
+    """On a 2 Mpc grid the conditional variances collapse to rounding noise
+    after about two dozen nodes.  The design must then stop gaining: the
+    error curve stays >= 0, never rises, equals a from-scratch recomputation
+    of every step's error (eigendecomposition solve on each problem's
+    independent nodes), and the independent sets stop growing while further
+    nodes are still chosen."""
+    probs = _tight_problems()
+    n = 40
+    nodes, errs = q.greedy_nodes(probs, n)
+    errs = np.array(errs)
+    total = len(probs)
+    assert np.all(errs >= 0.0)
+    assert np.all(np.diff(errs) <= 1e-13 * total)
+    again = np.array(q.design_errors(probs, nodes))
+    assert np.max(np.abs(again - errs)) <= 1e-12 * total
+    sets = q.effective_sets(probs, nodes)
+    assert max(len(s) for s in sets) < n
+    # the dependent nodes of a problem get weight 0 there; the weights of the
+    # independent ones reproduce the error
+    W = q.design_weights(probs, nodes)
+    for p, ((C, a), B) in enumerate(zip(probs, sets)):
+        dep = [k for k, j in enumerate(nodes) if j not in B]
+        assert np.all(W[p, dep] == 0.0)
+        e = q.expected_error(C, a, nodes, W[p])
+        assert abs(e - q.optimal_error(C, a, B)) <= 1e-12
+
+
+def test_dependent_duplicate_shell_gets_no_weight():
+    """A fine grid whose last shell repeats the first: once one copy is a node
+    the other is dependent (conditional variance 0) and gains nothing."""
+    C0 = _spd(10, 30)
+    idx = list(range(10)) + [0]
+    C = C0[np.ix_(idx, idx)]
+    a = np.random.default_rng(31).standard_normal(11)
+    nodes, errs = q.greedy_nodes([(C, a)], 11)
+    sets = q.effective_sets([(C, a)], nodes)
+    assert len(sets[0]) == 10 and not ({0, 10} <= set(sets[0]))
+    assert abs(errs[-1]) <= 1e-10 * float(a @ C @ a)
