@@ -198,6 +198,27 @@ int sim_backward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, co
 int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
                           int *nodes, double *err, double *w, void *stream);
 
+/* sim_quadrature_design without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same design and kernels, with the
+ * workspace in a fixed 64 MiB device array that each GPU holds for the life
+ * of the process instead of a per-call allocation.
+ *   cov, a, P, ntot, n   as for sim_quadrature_design
+ *   nodes    device [n] int out
+ *   err      device [n] FP64 out
+ *   w        device [P][n] FP64 out
+ *   stream   HIP stream (NULL = default)
+ * Asynchronous on the stream: no host copy, no synchronisation, no
+ * hipMalloc/hipFree and no memset (the kernels clear the state they need).
+ * SIM_EINVAL (nothing launched) for a null pointer, sizes out of range, or a
+ * design whose workspace (about 8 P ntot (n + 3) bytes; see
+ * sim_quadrature_design) exceeds 64 MiB -- for P = 2 problems, 400 fine
+ * shells and 70 nodes it is 0.5 MiB.  All calls on one GPU share its
+ * workspace: calls that overlap in time on one GPU (two streams or two host
+ * threads) race and give wrong results; calls in stream order are safe. */
+int sim_quadrature_design_noalloc(const double *cov, const double *a, int P, int ntot, int n,
+                                  int *nodes, double *err, double *w, void *stream);
+
 /* Reverse-mode derivative of sim_forward for a real loss.
  *   gT, gE    device [R][n_lm] complex128 cotangents dLoss/dRe a + i dLoss/dIm a
  *   grad_n    device [R][N][n_lm] complex, dtype of the noise, same convention

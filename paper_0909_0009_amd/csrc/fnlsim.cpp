@@ -1141,4 +1141,32 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
     return rc;
 }
 
+int sim_quadrature_design_noalloc(const double *cov, const double *a, int P, int ntot, int n,
+                                  int *nodes, double *err, double *w, void *stream)
+{
+    if (!cov || !a || !nodes || !err || !w)
+        return fail(nullptr, SIM_EINVAL, "a required pointer is NULL");
+    if (P < 1 || P > 65535) return fail(nullptr, SIM_EINVAL, "P = %d outside [1, 65535]", P);
+    if (ntot < 1 || ntot > 16384)
+        return fail(nullptr, SIM_EINVAL, "ntot = %d outside [1, 16384]", ntot);
+    if (n < 1 || n > ntot || n > fnl::kQuadMaxNodes)
+        return fail(nullptr, SIM_EINVAL, "n = %d outside [1, min(ntot, %d)]", n, fnl::kQuadMaxNodes);
+    const size_t need = fnl::quad_workspace_bytes(P, ntot, n);
+    if (need > fnl::kQuadScratchBytes)
+        return fail(nullptr, SIM_EINVAL,
+                    "design needs %zu bytes of workspace, above the fixed %zu-byte workspace of the "
+                    "no-allocation entry point (use sim_quadrature_design)",
+                    need, fnl::kQuadScratchBytes);
+    void *ws = nullptr;
+    hipError_t e = fnl::quad_scratch(&ws);
+    if (e != hipSuccess)
+        return fail(nullptr, SIM_EDEVICE, "fixed workspace lookup: %s", hipGetErrorString(e));
+    fnl::QuadState q{};
+    fnl::quad_bind(q, P, ntot, n, cov, a, ws);
+    e = fnl::quad_run(q, n, nodes, err, w, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return fail(nullptr, SIM_EDEVICE, "quadrature design: %s", hipGetErrorString(e));
+    return SIM_OK;
+}
+
 }  // extern "C"

@@ -1,5 +1,6 @@
 // quadrature.h -- launchers of the greedy radial-quadrature design kernels
-// (quadrature.hip), called by sim_quadrature_design in fnlsim.cpp.
+// (quadrature.hip), called by sim_quadrature_design and
+// sim_quadrature_design_noalloc in fnlsim.cpp.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -16,6 +17,10 @@ constexpr double kQuadDependent = 1e-10;
 // in chunks of this many, then the chunks in order).
 constexpr int kQuadPChunk = 32;
 constexpr int kQuadMaxNodes = 1024;
+// Size of the fixed device workspace behind sim_quadrature_design_noalloc
+// (64 MiB per GPU), and the number of devices it keeps an address for.
+constexpr size_t kQuadScratchBytes = size_t(64) << 20;
+constexpr int kQuadMaxDevices = 64;
 
 // Problem sizes and device state of one design run.  Arrays (device, FP64):
 //   C [P][ntot][ntot]  covariance of Phi on the fine grid, per problem
@@ -41,6 +46,10 @@ struct QuadState {
 // of a QuadState's arrays to such a workspace (256-byte aligned base).
 size_t quad_workspace_bytes(int P, int ntot, int n);
 void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws);
+
+// Device address of the fixed workspace on the current device (looked up
+// once per device).
+hipError_t quad_scratch(void **ptr);
 
 // The whole design on stream s, asynchronous: clears the workspace state it
 // needs, then n greedy steps, then the weights.  nodes [n] (int), err [n] and

@@ -18,9 +18,17 @@
 // a^T C a - |z|^2 per problem, summed in a fixed order.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "quadrature.h"
 
 namespace fnl {
+
+// Workspace of sim_quadrature_design_noalloc: a fixed device array, so that
+// callers that cannot allocate need no hipMalloc.  Each GPU the library runs
+// on holds its own copy (at its own address) until the process ends; host
+// code reaches it only through the address quad_scratch() looks up.
+static __device__ __align__(256) unsigned char scratch[kQuadScratchBytes];
 
 namespace {
 
@@ -259,6 +267,27 @@ void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const doub
     q.aCa = (double *)take(8 * (size_t)P);
     q.gpart = (double *)take(8 * (size_t)q.npc * ntot);
     q.chosen = take((size_t)ntot);
+}
+
+hipError_t quad_scratch(void **ptr)
+{
+    // one symbol lookup per device, made with that device current (the first
+    // call on it); the address is kept for later calls
+    static std::mutex mu;
+    static void *addr[kQuadMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kQuadMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
 }
 
 hipError_t quad_run(QuadState &q, int n, int *nodes, double *err, double *w, hipStream_t s)

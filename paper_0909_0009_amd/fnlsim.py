@@ -22,7 +22,7 @@ SIM_NSTAGE = 6
 STAGE_NAMES = ("radial_lin", "filter", "synth", "ring", "anal", "combine")
 
 EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_backward",
-           "sim_backward_seeded", "sim_quadrature_design",
+           "sim_backward_seeded", "sim_quadrature_design", "sim_quadrature_design_noalloc",
            "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
            "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
@@ -74,6 +74,8 @@ def lib():
         L.sim_noise.restype = ip
         L.sim_quadrature_design.argtypes = [vp, vp, ip, ip, ip, vp, vp, vp, vp]
         L.sim_quadrature_design.restype = ip
+        L.sim_quadrature_design_noalloc.argtypes = [vp, vp, ip, ip, ip, vp, vp, vp, vp]
+        L.sim_quadrature_design_noalloc.restype = ip
         L.sim_backward_seeded.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         L.sim_backward_seeded.restype = ip
         L.sim_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
@@ -137,6 +139,28 @@ def quadrature_design(cov, a, n, stream=None):
                                      ctypes.c_void_p(stream) if stream else None)
     _check(rc, None)
     return nodes, err, w
+
+
+def quadrature_design_noalloc(cov, a, n, nodes, err, w, stream=None):
+    """sim_quadrature_design_noalloc: the same design with no allocation in
+    the library, asynchronous on the stream.  nodes (int32 [n]), err
+    (float64 [n]) and w (float64 [P][n]) are caller-provided CUDA tensors."""
+    for t in (cov, a, err, w):
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError("cov, a, err and w must be contiguous CUDA float64 tensors")
+    if nodes.dtype != torch.int32 or not nodes.is_cuda or not nodes.is_contiguous():
+        raise TypeError("nodes must be a contiguous CUDA int32 tensor")
+    if cov.dim() != 3 or cov.shape[1] != cov.shape[2] or tuple(a.shape) != tuple(cov.shape[:2]):
+        raise ValueError("cov must be [P][ntot][ntot] and a [P][ntot]")
+    P, ntot, n = int(cov.shape[0]), int(cov.shape[1]), int(n)
+    if nodes.numel() != n or err.numel() != n or tuple(w.shape) != (P, n):
+        raise ValueError("nodes and err must hold n values and w [P][n]")
+    if stream is None:
+        stream = torch.cuda.current_stream().cuda_stream
+    rc = lib().sim_quadrature_design_noalloc(cov.data_ptr(), a.data_ptr(), P, ntot, n,
+                                             nodes.data_ptr(), err.data_ptr(), w.data_ptr(),
+                                             ctypes.c_void_p(stream) if stream else None)
+    _check(rc, None)
 
 
 class Simulator:

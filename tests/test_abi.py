@@ -142,3 +142,14 @@ def test_missing_library_fails_loudly(fs, monkeypatch, tmp_path):
     r, w, F, a, b = _args()
     with pytest.raises(RuntimeError, match="missing"):
         fs.Simulator(4, r, w, F, a, b)
+
+
+def test_noalloc_design_rejects_oversized_workspace_without_device(fs):
+    """The allocation-free quadrature design refuses, before any device call,
+    a design whose workspace exceeds its fixed 64 MiB (a full 2050-problem
+    design needs about 0.5 GB)."""
+    dummy = ctypes.c_void_p(16)
+    rc = fs.lib().sim_quadrature_design_noalloc(dummy, dummy, 2050, 400, 70, dummy, dummy, dummy,
+                                                None)
+    assert rc == fs.SIM_EINVAL
+    assert b"workspace" in fs.lib().sim_last_error(None)
