@@ -251,7 +251,7 @@ def time_batch(torch, fnlsim, inputs, precision, steps, warmup):
     probs = {}
     for i, (L, N) in enumerate(mix):
         if (L, N) not in probs:
-            probs[(L, N)] = inputs.problem(L, N)
+            probs[(L, N)] = inputs.problem(L, N, device="cuda")
             log(f"batch input {i + 1}/{len(mix)}: lmax {L}, {N} nodes ({time.time() - t0:.0f} s)")
     log(f"batch inputs ready in {time.time() - t0:.1f} s")
     for i, (L, N) in enumerate(mix):
@@ -294,6 +294,58 @@ def time_batch(torch, fnlsim, inputs, precision, steps, warmup):
             "speedup": round(ms_s / ms_b, 3), "max_rel_diff_vs_sequential": worst,
             "workload": "32 realizations, lmax in {128,256,512,1024}, 64..200 nodes "
                         "(default_rng(33)), n_theta = ceil((3L+1)/2), n_phi = 3L, f_NL = 50"}
+
+
+def time_ksw(torch, fnlsim, inputs, p, cfg, aT, aE, precision, steps, warmup):
+    """Cubic KSW statistic S_prim (Sect. 4) of one T+E realization at the
+    paper workload: the filtered maps A and B of all 200 radial nodes (400
+    syntheses on the 1537 x 3072 grid), the sky integral of A B^2 and the
+    radial sum, per step."""
+    L = cfg["lmax"]
+    al, be, ci = inputs.ksw_tables(p)
+    st = fnlsim.KswStatistic(L, p["r"], p["w"], al, be, ci, n_ring=cfg["ntheta"],
+                             n_phi=cfg["nphi"], precision=precision)
+    tT = torch.from_numpy(aT).cuda().reshape(1, -1)
+    tE = torch.from_numpy(aE).cuda().reshape(1, -1)
+    for _ in range(warmup):
+        st(tT, tE)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        S = st(tT, tE)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    st.close()
+    return {"ms": round(ms, 4), "statistics_per_s": round(1000.0 / ms, 3),
+            "S_prim": float(S[0]), "precision": precision,
+            "workload": f"lmax={L}, {len(p['r'])} radial nodes, {cfg['ntheta']}x{cfg['nphi']} grid"}
+
+
+def time_tqu(torch, fnlsim, p, cfg, aT, aE, steps, warmup):
+    """T, Q, U maps of one realization at the paper workload (FP64)."""
+    L = cfg["lmax"]
+    sim = fnlsim.Simulator(L, p["r"][:1], p["w"][:1], p["filter"][:, :1, :1], p["alpha"][:, :1],
+                           p["beta"][:, :1], n_ring=cfg["ntheta"], n_phi=cfg["nphi"])
+    tT = torch.from_numpy(aT).cuda().reshape(1, -1)
+    tE = torch.from_numpy(aE).cuda().reshape(1, -1)
+    for _ in range(warmup):
+        sim.tqu_maps(tT, tE)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        sim.tqu_maps(tT, tE)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    sim.close()
+    return {"ms": round(ms, 4), "realizations_per_s": round(1000.0 / ms, 2),
+            "map_bytes": 3 * cfg["ntheta"] * cfg["nphi"] * 8,
+            "workload": f"lmax={L}, T+Q+U on {cfg['ntheta']}x{cfg['nphi']} (FP64)"}
 
 
 def per_l_rel_err(a, ref, L):
@@ -347,8 +399,8 @@ def main():
                     help="skip the radial-quadrature design leg")
     ap.add_argument("--no-seeded", action="store_true",
                     help="skip the counter-based-noise forward leg")
-    ap.add_argument("--batch", action="store_true",
-                    help="also time the uneven 32-realization batch against sequential calls")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the uneven 32-realization batch leg")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -416,13 +468,22 @@ def main():
             grad["fp64"] = time_fwd_bwd(torch, fnlsim, inputs, "fp64", args.steps, args.warmup)
         log(f"fwd+bwd: {grad}")
         torch.cuda.empty_cache()
+    ksw = None
+    tqu = None
+    if args.workload == "paper":
+        ksw = {pr: time_ksw(torch, fnlsim, inputs, p, cfg, r32["aT"], r32["aE"], pr, args.steps,
+                            args.warmup) for pr in ("fp32", "fp64")}
+        log(f"ksw: {ksw}")
+        tqu = time_tqu(torch, fnlsim, p, cfg, r32["aT"], r32["aE"], args.steps, args.warmup)
+        log(f"tqu: {tqu}")
+        torch.cuda.empty_cache()
     quad = None
     if not args.no_quad:
         quad = time_quadrature(torch, fnlsim)
         log(f"quadrature design: {quad['ms']} ms")
         torch.cuda.empty_cache()
     batch = None
-    if args.batch:
+    if not args.no_batch:
         batch = {"fp32": time_batch(torch, fnlsim, inputs, "fp32", args.steps, args.warmup)}
         log(f"batch: {batch}")
         torch.cuda.empty_cache()
@@ -456,6 +517,8 @@ def main():
         "fp64": fp64,
         "mixed_vs_fp64_max_rel_err": err,
         "seeded": seeded,
+        "ksw_cubic_statistic": ksw,
+        "tqu_maps": tqu,
         "quadrature_design": quad,
         "fwd_bwd": grad,
         "batch": batch,

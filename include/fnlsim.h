@@ -219,6 +219,53 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
 int sim_quadrature_design_noalloc(const double *cov, const double *a, int P, int ntot, int n,
                                   int *nodes, double *err, double *w, void *stream);
 
+/* Cubic KSW statistic (Sect. 4): for data a^T, a^E and radial nodes r_k,
+ *   A(r_k, n) = sum_{i,j in T,E} sum_lm (C^-1)^{ij}_l alpha^i_l(r_k) a^j_lm Y_lm(n),
+ *   B(r_k, n) = the same with beta^i_l(r_k),
+ *   S_prim   = sum_k w_k r_k^2 int d^2n A(r_k, n) B(r_k, n)^2,
+ * the statistic whose normalisation gives the f_NL estimate of
+ * Eq. fast_est.  sim_ksw_init creates a context for it (destroy it with
+ * sim_destroy; the generator's calls reject it with SIM_ESTATE):
+ *   r, w     [Nk]          radial nodes (Mpc) and quadrature weights
+ *   alpha    [2][L+1][Nk]  alpha^i_l(r_k), i = T then E
+ *   beta     [2][L+1][Nk]  beta^i_l(r_k)
+ *   cinv     [L+1][2][2]   (C^-1)^{ij}_l, the inverse T/E spectrum matrix
+ *                          (rows of zeros leave a multipole out)
+ *   opts     nullable; n_ring, n_phi, precision and stream as for sim_init
+ *            (the grid integrates A B^2 exactly; with n_phi = 3L the one
+ *            aliased term is removed); mean_mode and tune must be 0
+ * Host arrays, FP64.  SIM_EINVAL for bad sizes, null pointers, non-finite
+ * values, Nk > 2048, or an n_phi whose two rings do not fit in LDS at the
+ * precision.  The two filtered maps of every node run through the same
+ * Legendre synthesis as the generator (FP32 matrix cores in SIM_FP32); the
+ * sky and radial sums are FP64.
+ * sim_ksw_cubic computes S_prim for R realizations:
+ *   aT, aE   device [R][n_lm] complex128 data
+ *   S        device [R] FP64 out
+ * Asynchronous on the context stream. */
+int sim_ksw_init(sim_ctx **out, int lmax, int nnode, const double *r, const double *w,
+                 const double *alpha, const double *beta, const double *cinv,
+                 const sim_opts *opts);
+int sim_ksw_cubic(sim_ctx *ctx, const void *aT, const void *aE, int R, double *S);
+
+/* Temperature and Stokes Q, U maps of R realizations (the production maps of
+ * Sect. 3, shown in fig. cmb_maps) on the context's Gauss-Legendre grid:
+ *   T = sum_lm a^T_lm Y_lm,   Q + i U = -sum_lm a^E_lm 2Y_lm  (no B modes),
+ * with the spin-2 harmonics raised from Y_lm by the eth operator (Condon-
+ * Shortley phase), every real field summed over m >= 0 with c_0 = 1,
+ * c_m = 2 (a^E_l0 and the imaginary part of m = 0 ignored, l < 2 of E
+ * ignored).
+ *   aT, aE   device [R][n_lm] complex128
+ *   maps     device [R][3][n_ring][n_phi] FP64: T, Q, U; rings north to
+ *            south (sim_get_grid), phi_j = 2 pi j / n_phi
+ * Runs in FP64 in every precision (the contraction has two real columns per
+ * map: vector FMAs next to the FP64 recurrence, then FP64 ring FFTs).  The
+ * first call allocates the context's spin-2 tables (about 40 (n_lm +
+ * 128 (L+1)) bytes) and a 96 npair (L+1)-byte spectrum buffer; asynchronous
+ * on the context stream afterwards.  Works on any context (generator or
+ * cubic statistic). */
+int sim_tqu_maps(sim_ctx *ctx, const void *aT, const void *aE, int R, void *maps);
+
 /* Reverse-mode derivative of sim_forward for a real loss.
  *   gT, gE    device [R][n_lm] complex128 cotangents dLoss/dRe a + i dLoss/dIm a
  *   grad_n    device [R][N][n_lm] complex, dtype of the noise, same convention

@@ -275,6 +275,121 @@ void orc_anal(int L, int nth, int nph, const double *x, const double *wq,
     free(rw);
 }
 
+/* -------------------------------------------- spin-2 harmonics (Q, U) */
+
+/* Spin-weighted Legendre functions sl_lm(x), l = 0..L, at one (m, s), for
+ * sY_lm(theta, phi) = sl_lm(cos theta) e^{i m phi} with the Condon-Shortley
+ * phase and sY_lm obtained from Y_lm by the spin-raising (eth) and -lowering
+ * operators.  Start: at l0 = max(|m|, |s|) the closed-form sum for sY_lm
+ * (Goldberg et al. 1967) has a single term,
+ *   (-1)^m sqrt((l+m)!(l-m)!(2l+1) / (4 pi (l+s)!(l-s)!))
+ *     C(l-s, r) C(l+s, r+s-m) (-1)^(l-r-s) sin^(2l-k)(theta/2) cos^k(theta/2),
+ * k = 2r + s - m, evaluated in log form.  Then the three-term recurrence of
+ * the Wigner d-functions in l, normalised by sqrt((2l+1)/(4 pi)):
+ *   l sqrt(P_{l+1}) f_{l+1} / sqrt(2l+3)
+ *     = sqrt(2l+1) (l(l+1) x + m s) f_l - (l+1) sqrt(P_l / (2l-1)) f_{l-1},
+ *   P_j = (j^2 - m^2)(j^2 - s^2).                                          */
+static void spin_lambda(int L, int m, int s, double x, double *out)
+{
+    for (int l = 0; l <= L; l++) out[l] = 0.0;
+    int am = m < 0 ? -m : m, as = s < 0 ? -s : s;
+    int l0 = am > as ? am : as;
+    if (l0 > L) return;
+    int l = l0, r0 = -1;
+    for (int r = 0; r <= l - s; r++) {
+        int j = r + s - m;
+        if (j >= 0 && j <= l + s) { r0 = r; break; }
+    }
+    double sh = sqrt(0.5 * (1.0 - x)), ch = sqrt(0.5 * (1.0 + x));
+    int k = 2 * r0 + s - m;
+    double lg = 0.5 * (lgamma(l + m + 1.0) + lgamma(l - m + 1.0) + log(2.0 * l + 1.0) -
+                       log(4.0 * ORC_PI) - lgamma(l + s + 1.0) - lgamma(l - s + 1.0));
+    lg += lgamma(l - s + 1.0) - lgamma(r0 + 1.0) - lgamma(l - s - r0 + 1.0);
+    lg += lgamma(l + s + 1.0) - lgamma(r0 + s - m + 1.0) - lgamma(l + m - r0 + 1.0);
+    double f0;
+    if ((2 * l - k > 0 && sh == 0.0) || (k > 0 && ch == 0.0)) {
+        f0 = 0.0;
+    } else {
+        lg += (2 * l - k) * log(sh > 0.0 ? sh : 1.0) + k * log(ch > 0.0 ? ch : 1.0);
+        int sgn = ((m + (l - r0 - s)) % 2 == 0) ? 1 : -1;
+        f0 = sgn * exp(lg);
+    }
+    out[l0] = f0;
+    double fm = 0.0, f = f0;
+    for (l = l0; l < L; l++) {
+        double P1 = ((double)(l + 1) * (l + 1) - (double)m * m) * ((double)(l + 1) * (l + 1) - (double)s * s);
+        double P0 = ((double)l * l - (double)m * m) * ((double)l * l - (double)s * s);
+        double fn = sqrt(2.0 * l + 3.0) / (l * sqrt(P1)) *
+                    (sqrt(2.0 * l + 1.0) * ((double)l * (l + 1) * x + (double)m * s) * f -
+                     (l + 1) * sqrt(P0 / (2.0 * l - 1.0)) * fm);
+        out[l + 1] = fn;
+        fm = f;
+        f = fn;
+    }
+}
+
+void orc_spin_lambda(int lmax, int m, int s, double x, double *out)
+{
+    spin_lambda(lmax, m, s, x, out);
+}
+
+/* Q and U of a pure-E polarisation field (B = 0) on rings x[0..nx):
+ *   Q + i U = -sum_{l>=2} sum_{m=-l..l} aE_lm 2Y_lm,
+ * with aE_{l,-m} = (-1)^m conj(aE_lm), every m summed directly, and a naive
+ * ring DFT with an integer twiddle index.                                  */
+void orc_synth_qu(int L, int nx, int nph, const double *x, const double *almE, double *Q,
+                  double *U)
+{
+    double *cs = (double *)malloc(sizeof(double) * 2 * nph);
+    for (int j = 0; j < nph; j++) {
+        cs[2 * j] = cos(2.0 * ORC_PI * j / nph);
+        cs[2 * j + 1] = sin(2.0 * ORC_PI * j / nph);
+    }
+#pragma omp parallel
+    {
+        double *lam = (double *)malloc(sizeof(double) * (L + 1));
+        double *gr = (double *)malloc(sizeof(double) * (2 * L + 1));
+        double *gi = (double *)malloc(sizeof(double) * (2 * L + 1));
+#pragma omp for schedule(dynamic, 1)
+        for (int k = 0; k < nx; k++) {
+            for (int m = -L; m <= L; m++) {
+                spin_lambda(L, m, 2, x[k], lam);
+                int am = m < 0 ? -m : m;
+                double sr = 0.0, si = 0.0;
+                for (int l = (am > 2 ? am : 2); l <= L; l++) {
+                    long id = idx_of(l, am);
+                    double ar = almE[2 * id], ai = am == 0 ? 0.0 : almE[2 * id + 1];
+                    if (m < 0) {  /* (-1)^m conj */
+                        double sg = (am % 2) ? -1.0 : 1.0;
+                        ar = sg * ar;
+                        ai = -sg * ai;
+                    }
+                    sr -= ar * lam[l];
+                    si -= ai * lam[l];
+                }
+                gr[m + L] = sr;
+                gi[m + L] = si;
+            }
+            for (int j = 0; j < nph; j++) {
+                double qr = 0.0, qi = 0.0;
+                for (int m = -L; m <= L; m++) {
+                    long t = ((long)m * j) % nph;
+                    if (t < 0) t += nph;
+                    double c = cs[2 * t], sn = cs[2 * t + 1];
+                    qr += gr[m + L] * c - gi[m + L] * sn;
+                    qi += gr[m + L] * sn + gi[m + L] * c;
+                }
+                Q[(size_t)k * nph + j] = qr;
+                U[(size_t)k * nph + j] = qi;
+            }
+        }
+        free(lam);
+        free(gr);
+        free(gi);
+    }
+    free(cs);
+}
+
 /* ------------------------------------------------------------ the model */
 
 static int problem_ok(const orc_problem *P)

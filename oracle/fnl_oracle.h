@@ -54,6 +54,16 @@ void orc_lambda_all(int lmax, double x, double *lam);
 void orc_synth(int lmax, int ntheta, int nphi, const double *x,
                const double *alm, double *map);
 
+/* Spin-weighted Legendre functions sl_lm(x) for l = 0..L at one (m, s):
+ * sY_lm = sl_lm(cos theta) e^{i m phi}, raised from Y_lm by eth (Condon-
+ * Shortley phase).  out [L+1], zero below l = max(|m|, |s|).               */
+void orc_spin_lambda(int lmax, int m, int s, double x, double *out);
+
+/* Stokes Q, U of a pure-E field on nx rings at x[] (any ring list), nph
+ * pixels each: Q + i U = -sum_{l>=2, all m} aE_lm 2Y_lm.  Q, U [nx][nph].   */
+void orc_synth_qu(int lmax, int nx, int nph, const double *x, const double *almE, double *Q,
+                  double *U);
+
 /* Analysis: alm_lm = sum_k omega_k (2 pi / nphi) sum_j map[k][j]
  * lambda_lm(x_k) e^{-i m phi_j}.                                           */
 void orc_anal(int lmax, int ntheta, int nphi, const double *x,

@@ -48,6 +48,10 @@ def lib():
         _lib.orc_noise.argtypes = [ip, ip, ctypes.c_ulonglong, vp]
         _lib.orc_noise.restype = None
         _lib.orc_adjoint.restype = ip
+        _lib.orc_spin_lambda.argtypes = [ip, ip, ip, dp, vp]
+        _lib.orc_spin_lambda.restype = None
+        _lib.orc_synth_qu.argtypes = [ip, ip, ip, vp, vp, vp, vp]
+        _lib.orc_synth_qu.restype = None
     return _lib
 
 
@@ -96,6 +100,32 @@ def synth(L, ntheta, nphi, alm):
     alm = _c128(alm)
     out = np.empty((ntheta, nphi))
     lib().orc_synth(L, ntheta, nphi, _ptr(x), _ptr(alm), _ptr(out))
+    return out
+
+
+def spin_lambda(L, m, s, x):
+    """sl_lm(x) for l = 0..L (spin-weighted Legendre functions, one m and s)."""
+    out = np.empty(L + 1)
+    lib().orc_spin_lambda(int(L), int(m), int(s), float(x), _ptr(out))
+    return out
+
+
+def synth_qu(L, x, nphi, almE):
+    """Stokes Q, U maps [len(x)][nphi] of a pure-E field on the rings x."""
+    x = _f64(x)
+    almE = _c128(almE)
+    Q = np.empty((x.size, nphi))
+    U = np.empty((x.size, nphi))
+    lib().orc_synth_qu(int(L), x.size, int(nphi), _ptr(x), _ptr(almE), _ptr(Q), _ptr(U))
+    return Q, U
+
+
+def synth_rings(L, x, nphi, alm):
+    """Scalar synthesis on an arbitrary ring list x (orc_synth)."""
+    x = _f64(x)
+    alm = _c128(alm)
+    out = np.empty((x.size, nphi))
+    lib().orc_synth(int(L), x.size, int(nphi), _ptr(x), _ptr(alm), _ptr(out))
     return out
 
 

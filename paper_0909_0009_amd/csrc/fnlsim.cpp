@@ -29,6 +29,7 @@ using fnl::Shape;
 struct sim_ctx {
     Shape sh{};
     Bufs b{};
+    int kind = 0;  // 0: map generator (sim_init), 1: cubic statistic (sim_ksw_init)
     hipStream_t stream = nullptr;
     int device = 0;
     std::string err;
@@ -258,6 +259,22 @@ int build_precision_tables(sim_ctx *c, const double *filter)
     const Shape &sh = c->sh;
     Bufs &b = c->b;
     const int L = sh.L, N = sh.N;
+    const size_t elem = sizeof(T);
+    if (!filter) {
+        // cubic statistic: twiddles, the filtered-map coefficients and the
+        // synthesis output only
+        int rc = 0;
+        using C2 = typename C2of<T>::type;
+        std::vector<C2> tw(sh.nphi);
+        for (int q = 0; q < sh.nphi; q++) {
+            const double a = 2.0 * kPi * (double)q / (double)sh.nphi;
+            tw[q].x = (T)std::cos(a);
+            tw[q].y = (T)(-std::sin(a));
+        }
+        if ((rc = upload(c, &b.tw, tw.data(), tw.size()))) return rc;
+        if ((rc = alloc_zero(c, &b.phi, elem * ((size_t)sh.nlm + fnl::kPhiPad) * sh.Cpad))) return rc;
+        return alloc_zero(c, &b.G, elem * (size_t)sh.npair * (L + 1) * 2 * sh.Cpad);
+    }
     // transposed, zero-padded filter [L+1][Kpad][Mpad]
     std::vector<T> FT((size_t)(L + 1) * b.Kpad * b.Mpad, T(0));
     for (int l = 0; l <= L; l++)
@@ -288,7 +305,6 @@ int build_precision_tables(sim_ctx *c, const double *filter)
     }
     rc = upload(c, &b.tw, tw.data(), tw.size());
     if (rc) return rc;
-    const size_t elem = sizeof(T);
     // zero rows past the last m block: the synthesis reads whole K-steps and
     // prefetches two K-steps ahead
     const size_t phib = elem * ((size_t)sh.nlm + fnl::kPhiPad) * sh.Cpad;
@@ -304,17 +320,27 @@ int build_precision_tables(sim_ctx *c, const double *filter)
 int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 *aE,
                 double2 *aTn, double2 *aEn, unsigned long long seed = 0);
 
+// Inputs of a cubic-statistic context (sim_ksw_init): tables [2][L+1][Nk]
+// (T then E) and the inverse spectra [L+1][2][2].
+struct KswIn {
+    const double *alpha, *beta, *cinv;
+};
+
 // Build a context; force_cf = 0 picks the column tile by the padding rule.
+// ksw != nullptr builds a cubic-statistic context over `nshell` radial nodes
+// (filter, alpha and beta unused): its synthesis runs the filtered maps A and
+// B of every node as 2 nshell "shells".
 int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double *w,
              const double *filter, const double *alpha, const double *beta, const sim_opts &o,
-             int force_cf)
+             int force_cf, const KswIn *ksw = nullptr)
 {
     if (lmax < 1 || lmax > 4096) return fail(nullptr, SIM_EINVAL, "lmax %d outside [1, 4096]", lmax);
-    if (nshell < 1 || nshell > 4096)
-        return fail(nullptr, SIM_EINVAL, "nshell %d outside [1, 4096]", nshell);
-    if (!r || !w || !filter || !alpha || !beta)
+    if (nshell < 1 || nshell > (ksw ? 2048 : 4096))
+        return fail(nullptr, SIM_EINVAL, "nshell %d outside [1, %d]", nshell, ksw ? 2048 : 4096);
+    if (!r || !w || (ksw ? (!ksw->alpha || !ksw->beta || !ksw->cinv) : (!filter || !alpha || !beta)))
         return fail(nullptr, SIM_EINVAL, "a required host array is NULL");
-    const int L = lmax, N = nshell;
+    const int L = lmax, Nk = nshell;
+    const int N = ksw ? 2 * nshell : nshell;
     const int min_ring = (3 * L + 2) / 2;
     const int nring = o.n_ring ? o.n_ring : min_ring;
     if (nring < min_ring)
@@ -338,12 +364,24 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     if (o.mean_mode != SIM_MEAN_SAMPLE && o.mean_mode != SIM_MEAN_ENSEMBLE)
         return fail(nullptr, SIM_EINVAL, "unknown mean_mode %d", o.mean_mode);
     if (o.max_batch < 0) return fail(nullptr, SIM_EINVAL, "max_batch < 0");
-    if (!all_finite(r, N) || !all_finite(w, N))
+    if (!all_finite(r, Nk) || !all_finite(w, Nk))
         return fail(nullptr, SIM_EINVAL, "r or w has a non-finite value");
-    if (!all_finite(filter, (size_t)(L + 1) * N * N))
-        return fail(nullptr, SIM_EINVAL, "filter has a non-finite value");
-    if (!all_finite(alpha, (size_t)(L + 1) * N) || !all_finite(beta, (size_t)(L + 1) * N))
-        return fail(nullptr, SIM_EINVAL, "alpha or beta has a non-finite value");
+    if (ksw) {
+        if (!all_finite(ksw->alpha, (size_t)2 * (L + 1) * Nk) ||
+            !all_finite(ksw->beta, (size_t)2 * (L + 1) * Nk))
+            return fail(nullptr, SIM_EINVAL, "alpha or beta has a non-finite value");
+        if (!all_finite(ksw->cinv, (size_t)4 * (L + 1)))
+            return fail(nullptr, SIM_EINVAL, "cinv has a non-finite value");
+        const size_t elem = o.precision == SIM_FP32 ? sizeof(float2) : sizeof(double2);
+        if (2 * elem * (size_t)fnl::ring_pad(nphi) > fnl::kMaxLds)
+            return fail(nullptr, SIM_EINVAL, "n_phi %d is too long for the cubic statistic at this precision",
+                        nphi);
+    } else {
+        if (!all_finite(filter, (size_t)(L + 1) * N * N))
+            return fail(nullptr, SIM_EINVAL, "filter has a non-finite value");
+        if (!all_finite(alpha, (size_t)(L + 1) * N) || !all_finite(beta, (size_t)(L + 1) * N))
+            return fail(nullptr, SIM_EINVAL, "alpha or beta has a non-finite value");
+    }
 
     Shape sh{};
     sh.L = L;
@@ -376,7 +414,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     sh.nlm = (long long)(L + 1) * (L + 2) / 2;
     sh.mean_mode = o.mean_mode;
     sh.fp32 = o.precision == SIM_FP32;
-    sh.lower = 1;
+    sh.lower = ksw ? 0 : 1;
     for (int l = 0; l <= L && sh.lower; l++)
         for (int i = 0; i < N && sh.lower; i++)
             for (int j = i + 1; j < N; j++)
@@ -389,6 +427,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     if (!c) return fail(nullptr, SIM_ENOMEM, "host allocation failed");
     c->sh = sh;
     c->stream = (hipStream_t)o.stream;
+    c->kind = ksw ? 1 : 0;
     Bufs &b = c->b;
 
     // ---- host tables (FP64)
@@ -416,15 +455,15 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             coef[fnl::crow(L, m) + (l - m)] = make_double2(A, B);
         }
     const int Npad = sh.Cpad / 2;
-    std::vector<double> W((size_t)2 * (L + 1) * Npad, 0.0);
-    for (int l = 0; l <= L; l++)
+    std::vector<double> W(ksw ? 0 : (size_t)2 * (L + 1) * Npad, 0.0);
+    for (int l = 0; l <= L && !ksw; l++)
         for (int i = 0; i < N; i++) {
             const double base = w[i] * r[i] * r[i];
             W[(size_t)l * Npad + i] = base * alpha[(size_t)l * N + i];
             W[(size_t)(L + 1 + l) * Npad + i] = base * beta[(size_t)l * N + i];
         }
-    std::vector<double> V((size_t)2 * (L + 1) * N, 0.0);
-    for (int X = 0; X < 2; X++)
+    std::vector<double> V(ksw ? 0 : (size_t)2 * (L + 1) * N, 0.0);
+    for (int X = 0; X < 2 && !ksw; X++)
         for (int l = 0; l <= L; l++) {
             const double *Fl = filter + (size_t)l * N * N;
             const double *Wl = W.data() + (size_t)(X * (L + 1) + l) * Npad;
@@ -436,7 +475,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             }
         }
     std::vector<double> mu(Npad, 0.0);
-    if (sh.mean_mode == SIM_MEAN_ENSEMBLE)
+    if (!ksw && sh.mean_mode == SIM_MEAN_ENSEMBLE)
         for (int i = 0; i < N; i++) {
             double acc = 0.0;
             for (int l = 0; l <= L; l++) {
@@ -447,6 +486,24 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             }
             mu[i] = std::sqrt(4.0 * kPi) * acc;
         }
+    // cubic statistic: P[l][k][map][j] = sum_i X^i_l(r_k) (C^-1)^{ij}_l (X = alpha for
+    // map A, beta for map B) folds the inverse spectra into the tables, and
+    // wr2[k] = w_k r_k^2 is the radial weight
+    std::vector<double> kP(ksw ? (size_t)(L + 1) * Nk * 4 : 0), kW(ksw ? Nk : 0);
+    if (ksw) {
+        for (int l = 0; l <= L; l++)
+            for (int k = 0; k < Nk; k++)
+                for (int map = 0; map < 2; map++) {
+                    const double *X = map ? ksw->beta : ksw->alpha;
+                    for (int j = 0; j < 2; j++) {
+                        double s = 0.0;
+                        for (int i = 0; i < 2; i++)
+                            s += X[((size_t)i * (L + 1) + l) * Nk + k] * ksw->cinv[(size_t)l * 4 + 2 * i + j];
+                        kP[(((size_t)l * Nk + k) * 2 + map) * 2 + j] = s;
+                    }
+                }
+        for (int k = 0; k < Nk; k++) kW[k] = w[k] * r[k] * r[k];
+    }
     std::vector<int> seedoff(L + 2, 0);
     for (int m = 0; m <= L; m++)
         seedoff[m + 1] = seedoff[m] + (L - m + 1 + fnl::kSeedStride - 1) / fnl::kSeedStride;
@@ -454,7 +511,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     // filter: a group is the column tiles of one l, which read the same F_l
     // (x < 0 marks an idle block)
     std::vector<int2> k1;
-    {
+    if (!ksw) {
         std::vector<std::vector<int4>> g1;
         std::vector<double> w1;
         for (int l = 0; l <= L; l++) {
@@ -480,7 +537,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             for (int ct = 0; ct < sh.nct; ct++) {
                 std::vector<int4> a, c4;
                 for (int pt = 0; pt < npt; pt++) a.push_back(make_int4(m, pt, ct, 0));
-                for (int lt = 0; lt < (L - m + 1 + rw - 1) / rw; lt++)
+                for (int lt = 0; lt < (L - m + 1 + rw - 1) / rw && !ksw; lt++)
                     c4.push_back(make_int4(m, lt, ct, 0));
                 g2.push_back(a);
                 w2.push_back((double)(L - m + 1));
@@ -488,7 +545,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
                 w4.push_back(1.0);
             }
         k2 = xcd_layout(g2, w2);
-        k4 = xcd_layout(g4, w4);
+        if (!ksw) k4 = xcd_layout(g4, w4);
     }
     b.nk2 = (int)k2.size();
     b.nk4 = (int)k4.size();
@@ -517,13 +574,18 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     UP(b.wq, wq);
     UP(b.lmm, lmm);
     UP(b.coef, coef);
-    UP(b.W, W);
-    UP(b.V, V);
-    UP(b.mu, mu);
+    if (ksw) {
+        UP(b.kswP, kP);
+        UP(b.kswW, kW);
+    } else {
+        UP(b.W, W);
+        UP(b.V, V);
+        UP(b.mu, mu);
+        UP(b.k1tiles, k1);
+        UP(b.k4tiles, k4);
+    }
     UP(b.seedoff, seedoff);
-    UP(b.k1tiles, k1);
     UP(b.k2tiles, k2);
-    UP(b.k4tiles, k4);
 #undef UP
     {
         void *p = nullptr;
@@ -533,13 +595,18 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
         b.lstart = (int *)p;
         if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 31) / 32)))) goto bad;
         b.cmin = (int *)p;
-        if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)sh.nct * 2 * sh.nlm))) goto bad;
-        b.part = (double2 *)p;
-        if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)2 * sh.nlm))) goto bad;
-        b.aL = (double2 *)p;
+        if (ksw) {
+            if ((rc = alloc_zero(c, &p, sizeof(double) * (size_t)np * Nk))) goto bad;
+            b.kswpart = (double *)p;
+        } else {
+            if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)sh.nct * 2 * sh.nlm))) goto bad;
+            b.part = (double2 *)p;
+            if ((rc = alloc_zero(c, &p, sizeof(double2) * (size_t)2 * sh.nlm))) goto bad;
+            b.aL = (double2 *)p;
+        }
     }
-    rc = sh.fp32 ? build_precision_tables<float>(c, filter)
-                 : build_precision_tables<double>(c, filter);
+    rc = sh.fp32 ? build_precision_tables<float>(c, ksw ? nullptr : filter)
+                 : build_precision_tables<double>(c, ksw ? nullptr : filter);
     if (rc) goto bad;
     {
         hipError_t e = fnl::launch_seed_init(sh, b, c->stream);
@@ -645,7 +712,7 @@ int sim_get_info(const sim_ctx *c, sim_info *info)
 {
     if (!c || !info) return SIM_EINVAL;
     info->lmax = c->sh.L;
-    info->nshell = c->sh.N;
+    info->nshell = c->kind == 1 ? c->sh.N / 2 : c->sh.N;
     info->n_ring = c->sh.nring;
     info->n_phi = c->sh.nphi;
     info->n_pair = c->sh.npair;
@@ -747,6 +814,7 @@ int sim_forward(sim_ctx *c, const void *noise, int R, const double *fnl, void *a
                 void *aT_nl, void *aE_nl)
 {
     if (!c) return SIM_EINVAL;
+    if (c->kind != 0) return fail(c, SIM_ESTATE, "not a map-generator context");
     if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
     if (!noise || !fnl || !aT || !aE) return fail(c, SIM_EINVAL, "a required pointer is NULL");
     for (int r = 0; r < R; r++)
@@ -769,6 +837,7 @@ int sim_forward_seeded(sim_ctx *c, const unsigned long long *seeds, int R, const
                        void *aT, void *aE, void *aT_nl, void *aE_nl)
 {
     if (!c) return SIM_EINVAL;
+    if (c->kind != 0) return fail(c, SIM_ESTATE, "not a map-generator context");
     if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
     if (!seeds || !fnl || !aT || !aE) return fail(c, SIM_EINVAL, "a required pointer is NULL");
     for (int r = 0; r < R; r++)
@@ -788,6 +857,7 @@ int sim_forward_seeded(sim_ctx *c, const unsigned long long *seeds, int R, const
 int sim_noise(sim_ctx *c, const unsigned long long *seeds, int R, void *noise)
 {
     if (!c) return SIM_EINVAL;
+    if (c->kind != 0) return fail(c, SIM_ESTATE, "not a map-generator context");
     if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
     if (!seeds || !noise) return fail(c, SIM_EINVAL, "a required pointer is NULL");
     const Shape &sh = c->sh;
@@ -825,6 +895,7 @@ static int backward_all(sim_ctx *c, const void *noise, const unsigned long long 
                         double *grad_fnl)
 {
     if (!c) return SIM_EINVAL;
+    if (c->kind != 0) return fail(c, SIM_ESTATE, "not a map-generator context");
     if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
     {
         // the reverse ring stage holds two rings of the grid in LDS
@@ -897,6 +968,7 @@ int sim_backward_seeded(sim_ctx *c, const unsigned long long *seeds, int R, cons
 int sim_debug_stage(sim_ctx *c, int stage, const void *in, void *out)
 {
     if (!c) return SIM_EINVAL;
+    if (c->kind != 0) return fail(c, SIM_ESTATE, "not a map-generator context");
     if (!in || !out) return fail(c, SIM_EINVAL, "in/out is NULL");
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
@@ -955,8 +1027,10 @@ int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
     if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
     *out = nullptr;
     if (!ctxs || count < 1) return fail(nullptr, SIM_EINVAL, "empty batch");
-    for (int i = 0; i < count; i++)
+    for (int i = 0; i < count; i++) {
         if (!ctxs[i]) return fail(nullptr, SIM_EINVAL, "context %d is NULL", i);
+        if (ctxs[i]->kind != 0) return fail(nullptr, SIM_EINVAL, "context %d is not a map generator", i);
+    }
     for (int i = 1; i < count; i++) {
         if (ctxs[i]->sh.fp32 != ctxs[0]->sh.fp32)
             return fail(nullptr, SIM_EINVAL, "contexts of one batch need the same precision");
@@ -1106,6 +1180,86 @@ int sim_batch_forward(sim_batch *b, const void *const *noise, const double *fnl,
         (e = hipEventRecord(b->ev_out, b->bs)) != hipSuccess ||
         (e = hipStreamWaitEvent(b->user, b->ev_out, 0)) != hipSuccess)
         return batch_fail(b, SIM_EDEVICE, "graph launch", e);
+    return SIM_OK;
+}
+
+int sim_ksw_init(sim_ctx **out, int lmax, int nnode, const double *r, const double *w,
+                 const double *alpha, const double *beta, const double *cinv, const sim_opts *opts)
+{
+    if (!out) return fail(nullptr, SIM_EINVAL, "out is NULL");
+    *out = nullptr;
+    sim_opts o{};
+    if (opts) o = *opts;
+    if (o.tune != 0) return fail(nullptr, SIM_EINVAL, "tune is not available for the cubic statistic");
+    if (o.mean_mode != SIM_MEAN_SAMPLE)
+        return fail(nullptr, SIM_EINVAL, "mean_mode does not apply to the cubic statistic (0)");
+    const KswIn k{alpha, beta, cinv};
+    return init_ctx(out, lmax, nnode, r, w, nullptr, nullptr, nullptr, o, 0, &k);
+}
+
+int sim_ksw_cubic(sim_ctx *c, const void *aT, const void *aE, int R, double *S)
+{
+    if (!c) return SIM_EINVAL;
+    if (c->kind != 1) return fail(c, SIM_ESTATE, "not a cubic-statistic context");
+    if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    if (!aT || !aE || !S) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    const Shape &sh = c->sh;
+    const Bufs &b = c->b;
+    hipStream_t s = c->stream;
+    for (int r = 0; r < R; r++) {
+        const double2 *t = (const double2 *)aT + sh.nlm * r;
+        const double2 *e = (const double2 *)aE + sh.nlm * r;
+        HIPCHECK(c, fnl::launch_ksw_filter(sh, b, t, e, s));
+        HIPCHECK(c, fnl::launch_synth(sh, b, b.phi, b.G, s));
+        HIPCHECK(c, fnl::launch_ksw_ring(sh, b, s));
+        HIPCHECK(c, fnl::launch_ksw_sum(sh, b, S + r, s));
+    }
+    return SIM_OK;
+}
+
+int sim_tqu_maps(sim_ctx *c, const void *aT, const void *aE, int R, void *maps)
+{
+    if (!c) return SIM_EINVAL;
+    if (R < 1) return fail(c, SIM_EINVAL, "R = %d < 1", R);
+    if (!aT || !aE || !maps) return fail(c, SIM_EINVAL, "a required pointer is NULL");
+    const Shape &sh = c->sh;
+    Bufs &b = c->b;
+    const int L = sh.L;
+    int rc;
+    if (!b.tqutab) {
+        // spin-2 coefficients per (m, l) in the recurrence table's layout:
+        // D^-1/2 (2m^2 - 2l, -l(l-1), 2 kappa, 2m (1-l), 2m kappa), zero for l < 2
+        std::vector<double> tab((size_t)(sh.nlm + (size_t)(L + 1) * fnl::kCoefPad) * 5, 0.0);
+        for (int m = 0; m <= L; m++)
+            for (int l = std::max(m, 2); l <= L; l++) {
+                const double dl = l, dm = m;
+                const double dinv = 1.0 / std::sqrt((dl - 1) * dl * (dl + 1) * (dl + 2));
+                const double kap = l > m ? std::sqrt((2 * dl + 1) * (dl * dl - dm * dm) / (2 * dl - 1)) : 0.0;
+                double *t = tab.data() + (size_t)(fnl::crow(L, m) + (l - m)) * 5;
+                t[0] = dinv * (2 * dm * dm - 2 * dl);
+                t[1] = -dinv * dl * (dl - 1);
+                t[2] = 2 * dinv * kap;
+                t[3] = 2 * dm * dinv * (1 - dl);
+                t[4] = 2 * dm * dinv * kap;
+            }
+        std::vector<double2> tw(sh.nphi);
+        for (int q = 0; q < sh.nphi; q++) {
+            const double a = 2.0 * kPi * (double)q / (double)sh.nphi;
+            tw[q] = make_double2(std::cos(a), -std::sin(a));
+        }
+        void *p = nullptr;
+        if ((rc = upload(c, &p, tab.data(), tab.size()))) return rc;
+        b.tqutab = (double *)p;
+        if ((rc = upload(c, &p, tw.data(), tw.size()))) return rc;
+        b.tqutw = (double2 *)p;
+        if ((rc = alloc_zero(c, &p, sizeof(double) * (size_t)sh.npair * 3 * (L + 1) * 4))) return rc;
+        b.tquG = (double *)p;
+    }
+    const size_t per = (size_t)3 * sh.nring * sh.nphi;
+    for (int r = 0; r < R; r++)
+        HIPCHECK(c, fnl::launch_tqu(sh, b, (const double2 *)aT + sh.nlm * r,
+                                    (const double2 *)aE + sh.nlm * r, (double *)maps + per * r,
+                                    c->stream));
     return SIM_OK;
 }
 

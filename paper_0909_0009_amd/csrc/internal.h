@@ -108,6 +108,15 @@ struct Bufs {
     void *G2;          // reverse pass: synthesis of the transposed radial sum (lazy)
     double *fpart;     // reverse pass: [npair * N] per-block dLoss/df_NL shares (lazy)
     double *fbar;      // reverse pass: [fbar_cap] dLoss/df_NL per realization (lazy)
+    // cubic statistic (a context whose N "shells" are the filtered maps A, B
+    // of N/2 radial nodes: shell 2k is A(r_k), shell 2k+1 is B(r_k))
+    double *kswP;      // [L+1][N/2][map A/B][data T/E] filter coefficients
+    double *kswW;      // [N/2] w_k r_k^2
+    double *kswpart;   // [npair][N/2] sky integral of A B^2 per ring pair and node
+    // T, Q, U maps (lazy, first sim_tqu_maps call)
+    double *tqutab;    // [nlm + (L+1) kCoefPad][5] spin-2 coefficients, crow layout
+    double2 *tqutw;    // [nphi] e^{-2 pi i q / nphi} in FP64
+    double *tquG;      // [npair][3][L+1][4] ring spectra (E re, O re, E im, O im)
     int fbar_cap;
     int Kpad, Mpad, nchq;
     int nk1, nk2, nk4;
@@ -170,6 +179,15 @@ hipError_t launch_filter_t(const Shape &sh, const Bufs &b, const void *phibar, v
 hipError_t launch_fbar(const Shape &sh, const Bufs &b, const double *fpart, const double2 *gT,
                        const double2 *gE, double *out, hipStream_t s);
 hipError_t launch_phi_to_api(const Shape &sh, const void *phi, double2 *api, hipStream_t s);
+// cubic statistic: filtered-map coefficients from the data, the ring stage
+// (A B^2 summed over each ring pair), and the weighted radial sum into *S
+hipError_t launch_ksw_filter(const Shape &sh, const Bufs &b, const double2 *aT, const double2 *aE,
+                             hipStream_t s);
+hipError_t launch_ksw_ring(const Shape &sh, const Bufs &b, hipStream_t s);
+hipError_t launch_ksw_sum(const Shape &sh, const Bufs &b, double *S, hipStream_t s);
+// T, Q, U maps [3][nring][nphi] (FP64) of one realization's a^T, a^E
+hipError_t launch_tqu(const Shape &sh, const Bufs &b, const double2 *aT, const double2 *aE,
+                      double *maps, hipStream_t s);
 hipError_t launch_api_to_phi(const Shape &sh, const double2 *api, void *phi, hipStream_t s);
 
 }  // namespace fnl

@@ -26,6 +26,7 @@ EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_ba
            "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
            "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
+           "sim_ksw_init", "sim_ksw_cubic", "sim_tqu_maps",
            "sim_destroy", "sim_last_error")
 
 _PRECISION = {"fp64": SIM_FP64, "fp32": SIM_FP32}
@@ -96,6 +97,13 @@ def lib():
         L.sim_batch_forward.restype = ip
         L.sim_batch_destroy.argtypes = [vp]
         L.sim_batch_destroy.restype = ip
+        L.sim_ksw_init.argtypes = [ctypes.POINTER(vp), ip, ip, vp, vp, vp, vp, vp,
+                                   ctypes.POINTER(_Opts)]
+        L.sim_ksw_init.restype = ip
+        L.sim_ksw_cubic.argtypes = [vp, vp, vp, ip, vp]
+        L.sim_ksw_cubic.restype = ip
+        L.sim_tqu_maps.argtypes = [vp, vp, vp, ip, vp]
+        L.sim_tqu_maps.restype = ip
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = ip
         L.sim_last_error.argtypes = [vp]
@@ -318,6 +326,18 @@ class Simulator:
         _check(rc, self._h)
         return gn, gf
 
+    def tqu_maps(self, aT, aE):
+        """T, Q, U maps [R][3][n_ring][n_phi] (CUDA float64) of harmonics aT, aE
+        ([R][n_lm] or [n_lm] CUDA complex128) on this context's grid."""
+        aT = aT.to(torch.complex128).contiguous().reshape(-1, self.n_lm)
+        aE = aE.to(torch.complex128).contiguous().reshape(-1, self.n_lm)
+        if aT.shape != aE.shape or not aT.is_cuda:
+            raise ValueError("aT and aE must be CUDA tensors of one shape")
+        R = aT.shape[0]
+        out = torch.empty((R, 3, self.n_ring, self.n_phi), dtype=torch.float64, device=aT.device)
+        _check(lib().sim_tqu_maps(self._h, aT.data_ptr(), aE.data_ptr(), R, out.data_ptr()), self._h)
+        return out
+
     def debug_stage(self, stage, inp):
         dev = inp.device
         if stage == SIM_STAGE_FILTER:
@@ -334,6 +354,56 @@ class Simulator:
             raise ValueError(stage)
         _check(lib().sim_debug_stage(self._h, stage, inp.data_ptr(), out.data_ptr()), self._h)
         return out
+
+
+class KswStatistic:
+    """Cubic KSW statistic S_prim (sim_ksw_init / sim_ksw_cubic)."""
+
+    def __init__(self, lmax, r, w, alpha, beta, cinv, n_ring=0, n_phi=0, precision="fp64",
+                 stream=None):
+        self.lmax = int(lmax)
+        r, w, alpha, beta, cinv = map(_f64, (r, w, alpha, beta, cinv))
+        self.nnode = int(r.shape[0])
+        L, Nk = self.lmax, self.nnode
+        if (alpha.shape != (2, L + 1, Nk) or beta.shape != (2, L + 1, Nk)
+                or cinv.shape != (L + 1, 2, 2) or w.shape != (Nk,)):
+            raise ValueError("alpha/beta must be [2][L+1][Nk], cinv [L+1][2][2], w [Nk]")
+        if stream is None and torch.cuda.is_available():
+            stream = torch.cuda.current_stream().cuda_stream
+        opts = _Opts(int(n_ring), int(n_phi), _PRECISION[precision], 0, 0,
+                     ctypes.c_void_p(stream) if stream else None, 0)
+        h = ctypes.c_void_p()
+        rc = lib().sim_ksw_init(ctypes.byref(h), L, Nk, r.ctypes.data, w.ctypes.data,
+                                alpha.ctypes.data, beta.ctypes.data, cinv.ctypes.data,
+                                ctypes.byref(opts))
+        _check(rc, None)
+        self._h = h
+        info = _Info()
+        _check(lib().sim_get_info(self._h, ctypes.byref(info)), self._h)
+        self.n_ring, self.n_phi, self.n_lm = info.n_ring, info.n_phi, int(info.n_lm)
+
+    def __call__(self, aT, aE):
+        """aT, aE: [R][n_lm] (or [n_lm]) CUDA complex128.  Returns S [R] as a
+        CUDA float64 tensor."""
+        aT = aT.to(torch.complex128).contiguous().reshape(-1, self.n_lm)
+        aE = aE.to(torch.complex128).contiguous().reshape(-1, self.n_lm)
+        if aT.shape != aE.shape or not aT.is_cuda:
+            raise ValueError("aT and aE must be CUDA tensors of one shape")
+        S = torch.empty(aT.shape[0], dtype=torch.float64, device=aT.device)
+        _check(lib().sim_ksw_cubic(self._h, aT.data_ptr(), aE.data_ptr(), aT.shape[0],
+                                   S.data_ptr()), self._h)
+        return S
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sim_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Batch:

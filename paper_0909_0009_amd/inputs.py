@@ -259,7 +259,7 @@ def _sph_bessel_table_torch(L, x):
             norm = norm + (2 * l - 1) * t_cur ** 2
             big = t_cur.abs() > 1e120
             # rescale where needed (a no-op elsewhere; no host sync per step)
-            f = torch.where(big, 1e-120, 1.0)
+            f = torch.where(big, torch.full_like(t_cur, 1e-120), torch.ones_like(t_cur))
             t_cur = t_cur * f
             t_next = t_next * f
             norm = norm * f * f
@@ -268,7 +268,8 @@ def _sph_bessel_table_torch(L, x):
                 stored[l - 1] = t_cur
                 stored_scale[l - 1] = scale
         lag = scale[None, :] - stored_scale
-        stored = stored * torch.where(lag == 0, 1.0, torch.where(lag == 1, 1e-120, 0.0))
+        one = torch.ones_like(stored)
+        stored = stored * torch.where(lag == 0, one, torch.where(lag == 1, 1e-120 * one, 0.0 * one))
         mag = 1.0 / torch.sqrt(norm)
         j0 = torch.sin(xs) / xs
         j1 = torch.sin(xs) / xs ** 2 - torch.cos(xs) / xs
@@ -303,6 +304,8 @@ def covariance_torch(L, r, device, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=40
         del J, JD
     out = C.cpu().numpy()
     del C
+    if not np.all(np.isfinite(out)):
+        raise FloatingPointError("covariance_torch produced a non-finite value")
     return out
 
 
@@ -336,6 +339,68 @@ def transfer_tables(L, r, seed=TRANSFER_SEED, centre=14000.0, width=150.0):
     beta = eE[:, None] * g[None, :]
     beta[:min(2, L + 1)] = 0.0
     return alpha, beta
+
+
+# ----------------------------------------------------- estimator tables
+
+def ksw_tables(p):
+    """Tables of the cubic KSW statistic (Sect. 4) on the problem's radial
+    nodes, as stand-ins for the CAMB-derived ones:
+
+    * alpha^i_l(r_k): the transfer tables themselves (i = T, E), [2][L+1][N];
+    * beta^i_l(r_k) = 4 pi int dk Delta^2(k)/k g^i_l(k) j_l(k r_k), which for
+      alpha of the same g equals int dr r^2 C_l(r_k, r) alpha^i_l(r); on the
+      nodes, sum_j C_l(r_k, r_j) w_j r_j^2 alpha^i_l(r_j), [2][L+1][N];
+    * (C^-1)_l: the inverse of the model spectrum matrix [[TT, TE], [TE, EE]],
+      C^{ij}_l = sum_{k,k'} W^i_lk C_l(r_k, r_k') W^j_lk' with W = w r^2 alpha,
+      [L+1][2][2]; zero for l < 2 (monopole and dipole are left out, and EE
+      vanishes there).  The synthetic T and E tables share one radial
+      profile, so this matrix has rank one (E carries no information T
+      lacks); its Moore-Penrose pseudo-inverse (eigenvalues below 1e-10 of
+      the largest dropped) stands in for the inverse.
+    """
+    C = p["cov"]
+    L1, N = p["alpha"].shape
+    wr2 = p["w"] * p["r"] ** 2
+    alpha = np.stack([p["alpha"], p["beta"]])
+    W = alpha * wr2[None, None, :]
+    beta = np.einsum("lkj,xlj->xlk", C, W)
+    spec = np.einsum("xlk,ylk->lxy", W, beta)
+    cinv = np.zeros((L1, 2, 2))
+    for l in range(2, L1):
+        S = 0.5 * (spec[l] + spec[l].T)
+        lam, U = np.linalg.eigh(S)
+        keep = lam > 1e-10 * lam.max()
+        cinv[l] = (U[:, keep] / lam[keep]) @ U[:, keep].T
+    return alpha, beta, cinv
+
+
+def model_spectrum(p):
+    """[L+1][2][2] T/E model spectrum C^{ij}_l = sum_kk' W^i_lk C_l(r_k, r_k') W^j_lk'
+    with W = w r^2 alpha (alpha = the T and E transfer tables)."""
+    wr2 = p["w"] * p["r"] ** 2
+    W = np.stack([p["alpha"], p["beta"]]) * wr2[None, None, :]
+    return np.einsum("xli,lij,ylj->lxy", W, p["cov"], W)
+
+
+def gaussian_data(p, seed):
+    """Seeded Gaussian T+E harmonic data with the model spectrum: a^X_lm with
+    E[a^i a^j*] = C^{ij}_l, complex for m > 0 (E|z|^2 = 1 per draw) and real
+    for m = 0; returns (aT, aE) [n_lm] complex128."""
+    spec = model_spectrum(p)
+    L = spec.shape[0] - 1
+    ls, ms = lm_arrays(L)
+    rng = np.random.default_rng(seed)
+    z = rng.standard_normal((2, ls.size, 2))
+    s = 1.0 / math.sqrt(2.0)
+    zc = np.where(ms == 0, z[:, :, 0], s * z[:, :, 0]) + 1j * np.where(ms == 0, 0.0, s * z[:, :, 1])
+    out = np.zeros((2, ls.size), dtype=np.complex128)
+    for l in range(L + 1):
+        lam, U = np.linalg.eigh(0.5 * (spec[l] + spec[l].T))
+        M = U * np.sqrt(np.maximum(lam, 0.0))[None, :]
+        sel = ls == l
+        out[:, sel] = M @ zc[:, sel]
+    return out[0], out[1]
 
 
 # ------------------------------------------------------------------ noise

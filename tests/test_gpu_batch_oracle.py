@@ -34,6 +34,19 @@ def fs():
     return fnlsim
 
 
+def test_gpu_covariance_matches_numpy():
+    """The batch inputs use the covariance evaluated with torch on the GPU;
+    it agrees with the numpy evaluation to rounding, on both Bessel
+    recurrence branches and with rescaling (small k r)."""
+    L, N = 300, 6
+    r, _ = inputs.radial_nodes(N)
+    C = inputs.covariance(L, r)
+    Cg = inputs.covariance_torch(L, r, "cuda")
+    err = np.max(np.abs(C - Cg)) / np.max(np.abs(C))
+    print(f"GPU covariance vs numpy: {err:.2e}", flush=True)
+    assert err <= 1e-13
+
+
 def _col_tile(N):
     """The default column tile: 16 CF columns, CF in 5..1 giving the least
     padding of the 2N real columns (the first such CF from 5 down)."""
