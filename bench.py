@@ -170,19 +170,31 @@ def time_seeded(torch, sim, cfg, steps, warmup):
             "sim_noise_values_per_s": round(nvals / gen_ms * 1e3, 1)}
 
 
-def time_quadrature(torch, fnlsim, P=2050, ntot=400, n=70, rank=48):
+def time_quadrature(torch, fnlsim, inputs, L=1024, ntot=400, n=70):
     """Greedy radial-quadrature design (sim_quadrature_design) at the size of
-    a full design: P = 2 (1024 + 1) problems (l = 0..1024, T and E), a
-    400-shell fine grid, 70 nodes.  Synthetic covariances: rank-48 Gram
-    matrices plus a 1e-3 ridge, built on the GPU; a = the trapezoid rule of a
-    unit grid.  The call is synchronous; the best of 3 after one warm-up."""
-    g = torch.Generator(device="cuda").manual_seed(5)
-    A = torch.randn((P, ntot, rank), dtype=torch.float64, device="cuda", generator=g)
-    cov = torch.bmm(A, A.transpose(1, 2).contiguous()) / rank
-    cov += 1e-3 * torch.eye(ntot, dtype=torch.float64, device="cuda")
-    del A
-    a = torch.ones((P, ntot), dtype=torch.float64, device="cuda")
-    a[:, 0] = a[:, -1] = 0.5
+    a full design: the synthetic covariance of Eq. cov_phi on a 400-shell
+    fine grid over [13000, 15000] Mpc (evaluated on the GPU), P = 2 (L + 1)
+    problems (l = 0..1024, T and E) with the fine-sum weights dr r^2 X_l(r)
+    of the synthetic transfer tables, each scaled to unit a^T C a; 70 nodes.
+    The call is synchronous; the best of 3 after one warm-up."""
+    import numpy as np
+    r = np.linspace(13000.0, 15000.0, ntot)
+    C = inputs.covariance_torch(L, r, "cuda", as_tensor=True)
+    alpha, beta = inputs.transfer_tables(L, r)
+    dr = np.zeros(ntot)
+    dr[:-1] += 0.5 * np.diff(r)
+    dr[1:] += 0.5 * np.diff(r)
+    P = 2 * (L + 1)
+    a = torch.empty((P, ntot), dtype=torch.float64, device="cuda")
+    a[0::2] = torch.from_numpy(dr * r * r * alpha).cuda()
+    a[1::2] = torch.from_numpy(dr * r * r * beta).cuda()
+    cov = torch.empty((P, ntot, ntot), dtype=torch.float64, device="cuda")
+    cov[0::2] = C
+    cov[1::2] = C
+    del C
+    s = torch.einsum("pi,pij,pj->p", a, cov, a)
+    s = torch.where(s > 0, s, torch.ones_like(s))
+    cov /= s[:, None, None]
     torch.cuda.synchronize()
     fnlsim.quadrature_design(cov, a, n)
     best = float("inf")
@@ -191,16 +203,18 @@ def time_quadrature(torch, fnlsim, P=2050, ntot=400, n=70, rank=48):
         nodes, err, _ = fnlsim.quadrature_design(cov, a, n)
         best = min(best, time.perf_counter() - t0)
     del cov, a
-    # algorithmic bytes: C read once (b = C a), then per step k the gain
-    # reads (d, e), the update reads k earlier columns, row sel of C and
+    # algorithmic bytes: C read once (b = C a), then per step k the gains read
+    # (d, e, C_jj), the update reads k earlier columns, row sel of C and
     # (d, e), and writes column k, d and e
     pn = 8.0 * P * ntot
-    byts = pn * ntot + sum(pn * (2 + k + 1 + 2 + 3) for k in range(n))
+    byts = pn * ntot + sum(pn * (3 + k + 1 + 2 + 3) for k in range(n))
     return {"ms": round(best * 1e3, 3), "problems": P, "fine_shells": ntot, "nodes": n,
             "algorithmic_bytes": byts, "achieved_GBps": round(byts / best / 1e9, 1),
             "final_error_rel": float(err[-1] / (err[0] + 1e-300)),
-            "workload": "rank-48 Gram covariances + 1e-3 ridge (synthetic), P = 2050, "
-                        "400-shell fine grid, 70 greedy nodes"}
+            "error_curve_10_30_50_70": [float(err[k - 1]) for k in (10, 30, 50, 70)],
+            "workload": "synthetic covariance of Eq. cov_phi on 400 fine shells over "
+                        "[13000, 15000] Mpc, l = 0..1024 x (T, E) problems scaled to unit "
+                        "a^T C a, 70 greedy nodes"}
 
 
 def time_fwd_bwd(torch, fnlsim, inputs, precision, steps, warmup):
@@ -234,8 +248,16 @@ def time_fwd_bwd(torch, fnlsim, inputs, precision, steps, warmup):
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    # five Legendre transforms per step (forward synthesis and analysis; the
+    # reverse pass's adjoint synthesis, Phi_L recomputation and adjoint
+    # analysis), each 2 n_pair n_lm (2N) flop
+    lflop = 5 * 2.0 * sim.n_pair * sim.n_lm * 2 * N
+    peak = PEAK["fp64_mfma_TFs"] if precision == "fp64" else PEAK["fp32_mfma_TFs"]
     sim.close()
     return {"value": round(1000.0 / ms, 3), "unit": "fwd+bwd maps/s", "ms_per_step": round(ms, 4),
+            "legendre_flop_per_step": lflop,
+            "legendre_TFLOPs_over_whole_step": round(lflop / ms / 1e9, 2),
+            "frac_of_mfma_peak_whole_step": round(lflop / ms / 1e9 / peak, 4),
             "workload": f"lmax={L}, {N} radial nodes, {cfg['ntheta']}x{cfg['nphi']} grid, "
                         f"gradients w.r.t. the noise and f_NL"}
 
@@ -359,28 +381,77 @@ def per_l_rel_err(a, ref, L):
     return float(np.max(num[ok] / den[ok]))
 
 
-def cpu_baseline(p, cfg, noise_np, nsample):
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _omp_threads(n):
+    """Set the OpenMP thread count of the oracle's runtime (libgomp) for the
+    following parallel regions; returns False if it cannot be set."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+        gomp.omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def cpu_baseline(p, cfg, noise_np, nsample, nsample1=1):
     """The FP64 oracle as it stands, on `nsample` of the N shells (transfer
     tables zeroed elsewhere: the oracle then evaluates only those shells).
-    Work per shell is identical, so maps/s = 1 / (t * N / nsample)."""
+    Work per shell is identical, so maps/s = 1 / (t * N / nsample).  Timed
+    on every usable host thread, then on one thread with `nsample1` shells."""
     import numpy as np
     from oracle import fnl_oracle
     L, N = cfg["lmax"], cfg["nshell"]
-    keep = np.linspace(N // 4, 3 * N // 4, nsample).astype(int)
-    al = np.zeros_like(p["alpha"])
-    be = np.zeros_like(p["beta"])
-    al[:, keep] = p["alpha"][:, keep]
-    be[:, keep] = p["beta"][:, keep]
-    P = fnl_oracle.Problem(L, p["r"], p["w"], p["filter"], al, be)
-    fnl_oracle.lib()
-    t0 = time.perf_counter()
-    P.forward(noise_np, cfg["fnl"])
-    t = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count()
+
+    def run(ns):
+        keep = np.linspace(N // 4, 3 * N // 4, ns).astype(int)
+        al = np.zeros_like(p["alpha"])
+        be = np.zeros_like(p["beta"])
+        al[:, keep] = p["alpha"][:, keep]
+        be[:, keep] = p["beta"][:, keep]
+        P = fnl_oracle.Problem(L, p["r"], p["w"], p["filter"], al, be)
+        fnl_oracle.lib()
+        t0 = time.perf_counter()
+        P.forward(noise_np, cfg["fnl"])
+        return time.perf_counter() - t0
+
+    try:
+        threads = len(os.sched_getaffinity(0))
+    except AttributeError:
+        threads = os.cpu_count()
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or threads
+    _omp_threads(threads)
+    t = run(nsample)
+    one = None
+    if nsample1 and _omp_threads(1):
+        t1 = run(nsample1)
+        _omp_threads(threads)
+        one = {"value": 1.0 / (t1 * N / nsample1), "unit": "maps/s", "cores": 1,
+               "sample": f"{nsample1} of {N} shells in {t1:.1f} s, scaled by {N}/{nsample1}"}
     return {"value": 1.0 / (t * N / nsample), "unit": "maps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{nsample} of {N} shells at lmax {L} (filter rows, synthesis, square, "
                       f"analysis and radial sums of those shells) in {t:.1f} s, scaled by "
-                      f"{N}/{nsample}"}
+                      f"{N}/{nsample}",
+            "one_core": one,
+            "paper_context": {"value": 8.3e-4, "unit": "maps/s",
+                              "hardware": "one Intel Xeon core at 2.33 GHz",
+                              "workload": "lmax 1024, HEALPix nside 512, 70 radial shells "
+                                          "(about 20 minutes per T+E map)",
+                              "shells_per_s": 0.058,
+                              "note": "the paper's own timing, not the same workload "
+                                      "(70 instead of 200 shells, HEALPix instead of the "
+                                      "exact Gauss-Legendre grid): compare per shell"}}
 
 
 def main():
@@ -479,7 +550,7 @@ def main():
         torch.cuda.empty_cache()
     quad = None
     if not args.no_quad:
-        quad = time_quadrature(torch, fnlsim)
+        quad = time_quadrature(torch, fnlsim, inputs)
         log(f"quadrature design: {quad['ms']} ms")
         torch.cuda.empty_cache()
     batch = None

@@ -111,3 +111,60 @@ def phi_nl_sample(alm, L):
     sq = square_coeffs(alm, L)
     sq[0] = 0j
     return sq
+
+
+def wigner3j_float(j1, j2, j3, m1, m2, m3):
+    """The same Racah formula in FP64: log-factorials (lgamma) for every
+    factor, the alternating sum added exactly-rounded (math.fsum).  For the
+    brute force at l ~ 32, where exact rationals get slow; checked against
+    wigner3j_exact at small l."""
+    if m1 + m2 + m3 != 0 or j3 < abs(j1 - j2) or j3 > j1 + j2:
+        return 0.0
+    if abs(m1) > j1 or abs(m2) > j2 or abs(m3) > j3:
+        return 0.0
+    lf = lambda n: math.lgamma(n + 1.0)
+    half = 0.5 * (lf(j1 + j2 - j3) + lf(j1 - j2 + j3) + lf(-j1 + j2 + j3) - lf(j1 + j2 + j3 + 1)
+                  + lf(j1 + m1) + lf(j1 - m1) + lf(j2 + m2) + lf(j2 - m2) + lf(j3 + m3) + lf(j3 - m3))
+    kmin = max(0, j2 - j3 - m1, j1 - j3 + m2)
+    kmax = min(j1 + j2 - j3, j1 - m1, j2 + m2)
+    terms = []
+    for k in range(kmin, kmax + 1):
+        lg = half - (lf(k) + lf(j3 - j2 + k + m1) + lf(j3 - j1 + k - m2) + lf(j1 + j2 - j3 - k)
+                     + lf(j1 - k - m1) + lf(j2 - k + m2))
+        terms.append((-1.0) ** k * math.exp(lg))
+    sign = -1.0 if (j1 - j2 - m3) % 2 else 1.0
+    return sign * math.fsum(terms)
+
+
+@lru_cache(maxsize=None)
+def gaunt_float(l1, m1, l2, m2, l, m):
+    """int Y_l1m1 Y_l2m2 Y*_lm dOmega with wigner3j_float."""
+    if m1 + m2 != m or (l1 + l2 + l) % 2:
+        return 0.0
+    w0 = wigner3j_float(l1, l2, l, 0, 0, 0)
+    if w0 == 0.0:
+        return 0.0
+    w1 = wigner3j_float(l1, l2, l, m1, m2, -m)
+    val = math.sqrt((2 * l1 + 1) * (2 * l2 + 1) * (2 * l + 1) / (4.0 * math.pi)) * w0 * w1
+    return -val if m % 2 else val
+
+
+def square_coeffs_float(alm, L, outputs):
+    """[Phi^2]_lm at the listed (l, m) outputs, by the Gaunt sum in FP64."""
+    full = _full(alm, L)
+    out = []
+    for l, m in outputs:
+        acc = 0j
+        for l1 in range(L + 1):
+            for l2 in range(abs(l - l1), min(L, l + l1) + 1):
+                if (l1 + l2 + l) % 2:
+                    continue
+                for m1 in range(-l1, l1 + 1):
+                    m2 = m - m1
+                    if abs(m2) > l2:
+                        continue
+                    gv = gaunt_float(l1, m1, l2, m2, l, m)
+                    if gv:
+                        acc += full[(l1, m1)] * full[(l2, m2)] * gv
+        out.append(acc)
+    return out

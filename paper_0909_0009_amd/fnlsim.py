@@ -171,6 +171,21 @@ def quadrature_design_noalloc(cov, a, n, nodes, err, w, stream=None):
     _check(rc, None)
 
 
+def design_tables(nodes, w, lmax):
+    """Node radii and radial tables for sim_init from a quadrature design over
+    the 2 (lmax + 1) problems (l, T) and (l, E) in that order (problem 2l is T,
+    2l + 1 is E): the designed weights already include dr r^2 X_l(r), so they
+    enter as alpha, beta with w = 1 and r = 1 (W^X_li = w_i r_i^2 X_l(r_i)).
+    w: [2 (lmax+1)][n] weights (host array or tensor).  Returns (nodes, r, w,
+    alpha, beta) with alpha, beta [lmax+1][n]."""
+    W = w.detach().cpu().numpy() if hasattr(w, "detach") else np.asarray(w, dtype=np.float64)
+    n = W.shape[1]
+    if W.shape[0] != 2 * (lmax + 1):
+        raise ValueError("w must have 2 (lmax + 1) rows (l, T) then (l, E)")
+    return (np.asarray(nodes), np.ones(n), np.ones(n), np.ascontiguousarray(W[0::2]),
+            np.ascontiguousarray(W[1::2]))
+
+
 class Simulator:
     """One context of the map generator (see include/fnlsim.h)."""
 

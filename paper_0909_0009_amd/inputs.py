@@ -280,11 +280,13 @@ def _sph_bessel_table_torch(L, x):
     return out
 
 
-def covariance_torch(L, r, device, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=4096, kchunk=1024):
+def covariance_torch(L, r, device, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=4096, kchunk=1024,
+                     as_tensor=False):
     """covariance() evaluated with torch FP64 on `device` (a GPU makes the
     paper-scale tables take about a second instead of minutes): the same k
     grid, trapezoid rule in ln k and Bessel recurrences; sums in another
-    order, so the result agrees with covariance() to rounding."""
+    order, so the result agrees with covariance() to rounding.  as_tensor
+    returns the device tensor instead of a host array."""
     import torch
     r_np = np.asarray(r, dtype=np.float64)
     k_np = np.geomspace(kmin, kmax, nk)
@@ -302,10 +304,12 @@ def covariance_torch(L, r, device, A=1.7e-8, ns=0.96, kmin=1e-5, kmax=0.2, nk=40
         JD = (J * Dc[None, None, :]).contiguous()
         C += torch.matmul(JD, J.transpose(1, 2).contiguous())
         del J, JD
+    if not bool(torch.isfinite(C).all()):
+        raise FloatingPointError("covariance_torch produced a non-finite value")
+    if as_tensor:
+        return C
     out = C.cpu().numpy()
     del C
-    if not np.all(np.isfinite(out)):
-        raise FloatingPointError("covariance_torch produced a non-finite value")
     return out
 
 

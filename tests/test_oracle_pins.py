@@ -184,6 +184,69 @@ def test_phi_nl_matches_gaunt_bruteforce(orc, L):
     assert np.max(np.abs(out["aT_nl"] - ref)) < 1e-12 * np.max(np.abs(ref))
 
 
+def test_racah_3j_matches_sympy():
+    """The exact Racah 3j of oracle/gaunt.py against sympy.physics.wigner for
+    every j1, j2 <= 4 and every admissible j3, m1, m2; and the FP64 version
+    against the exact one up to j = 12."""
+    from sympy.physics.wigner import wigner_3j
+    for j1 in range(5):
+        for j2 in range(5):
+            for j3 in range(abs(j1 - j2), j1 + j2 + 1):
+                for m1 in range(-j1, j1 + 1):
+                    for m2 in range(-j2, j2 + 1):
+                        m3 = -m1 - m2
+                        if abs(m3) > j3:
+                            continue
+                        ref = float(wigner_3j(j1, j2, j3, m1, m2, m3))
+                        assert abs(gaunt.wigner3j(j1, j2, j3, m1, m2, m3) - ref) <= 1e-15
+    rng = np.random.default_rng(2)
+    for _ in range(400):
+        j1, j2 = (int(v) for v in rng.integers(0, 13, 2))
+        j3 = int(rng.integers(abs(j1 - j2), min(12, j1 + j2) + 1))
+        m1 = int(rng.integers(-j1, j1 + 1))
+        m2 = int(rng.integers(-j2, j2 + 1))
+        if abs(m1 + m2) > j3:
+            continue
+        ex = gaunt.wigner3j(j1, j2, j3, m1, m2, -m1 - m2)
+        assert abs(gaunt.wigner3j_float(j1, j2, j3, m1, m2, -m1 - m2) - ex) <= 1e-13
+
+
+def test_phi_nl_every_shell_at_l12(orc):
+    """lmax 12, three shells (identity filter): each shell's Phi_NL against the
+    exact Gaunt brute force."""
+    L, N = 12, 3
+    rng = np.random.default_rng(12)
+    noise = np.stack([rand_alm(L, rng) for _ in range(N)])
+    one = np.ones(N)
+    P = orc.Problem(L, one, one, np.broadcast_to(np.eye(N), (L + 1, N, N)).copy(),
+                    np.ones((L + 1, N)), np.ones((L + 1, N)))
+    out = P.forward(noise, 0.0, want_phi=True)
+    for i in range(N):
+        ref = np.array(gaunt.phi_nl_sample(noise[i], L))
+        assert np.max(np.abs(out["phiNL"][i] - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_phi_nl_two_shells_at_l32_sampled(orc):
+    """lmax 32 on two shells: sampled coefficients of Phi_NL against the Gaunt
+    sum with FP64 3j symbols (log-factorial Racah formula).  The alternating
+    Racah sum cancels more as the j grow (to 96 here), so the FP64 3j, exact
+    to 1e-13 at j <= 12, carries ~1e-10 at these l: the bar is 5e-9 of the
+    largest coefficient (a dropped term or wrong sign is O(1))."""
+    L, N = 32, 2
+    rng = np.random.default_rng(32)
+    noise = np.stack([rand_alm(L, rng) for _ in range(N)])
+    one = np.ones(N)
+    P = orc.Problem(L, one, one, np.broadcast_to(np.eye(N), (L + 1, N, N)).copy(),
+                    np.ones((L + 1, N)), np.ones((L + 1, N)))
+    out = P.forward(noise, 0.0, want_phi=True)
+    outs = [(1, 0), (2, 1), (7, 3), (12, 12), (20, 5), (31, 30), (32, 0), (32, 32)]
+    for i in range(N):
+        ref = np.array(gaunt.square_coeffs_float(noise[i], L, outs))
+        got = np.array([out["phiNL"][i][l * (l + 1) // 2 + m] for l, m in outs])
+        scale = np.max(np.abs(out["phiNL"][i]))
+        assert np.max(np.abs(got - ref)) < 5e-9 * scale
+
+
 def test_phi_nl_gaunt_on_paper_grid_shape(orc):
     """The grid size rule ntheta = ceil((3L+1)/2), nphi = 3L+1 is what makes
     the brute-force equality exact; one ring fewer breaks it."""
