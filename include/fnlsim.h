@@ -79,7 +79,7 @@ enum {
     SIM_ESTATE = -4   /* call not valid in the context's current state      */
 };
 
-enum { SIM_FP64 = 0, SIM_FP32 = 1 };
+enum { SIM_FP64 = 0, SIM_FP32 = 1, SIM_BF16X3 = 2, SIM_BF16X6 = 3 };
 enum { SIM_MEAN_SAMPLE = 0, SIM_MEAN_ENSEMBLE = 1 };
 
 /* Options; zero-initialised fields take the defaults. */
@@ -88,8 +88,14 @@ typedef struct {
     int n_phi;      /* pixels per ring; 0 -> 3L if that is of the form 2^a 3^b 5^c,
                        else the next such length; must be >= 3L, of that form,
                        and <= 8192                                                 */
-    int precision;  /* SIM_FP64 (contractions in FP64) or SIM_FP32 (FP32 matrix
-                       cores, FP64 Legendre recurrence and radial sums)            */
+    int precision;  /* SIM_FP64 (contractions in FP64), SIM_FP32 (FP32 matrix
+                       cores, FP64 Legendre recurrence and radial sums), or the
+                       split-BF16 forms of the Legendre transforms: every FP32
+                       operand as 2 (SIM_BF16X3: 3 piece products) or 3
+                       (SIM_BF16X6: 6 products) BF16 pieces on the BF16 matrix
+                       cores with FP32 accumulation; their noise is complex64
+                       like SIM_FP32.  The reverse pass, batches and the cubic
+                       statistic take SIM_FP64 or SIM_FP32 only                 */
     int mean_mode;  /* SIM_MEAN_SAMPLE or SIM_MEAN_ENSEMBLE                        */
     int max_batch;  /* reserved; 0                                                 */
     void *stream;   /* hipStream_t for every launch; NULL = default stream         */
@@ -304,15 +310,29 @@ int sim_get_info(const sim_ctx *ctx, sim_info *info);
  * host arrays. */
 int sim_get_grid(const sim_ctx *ctx, double *x, double *w);
 
-/* Uneven batch: several contexts (any lmax, nshell, same precision and
- * stream) run as one grouped launch per stage.  The contexts must outlive
- * the batch. */
+/* Uneven batch: several distinct contexts (any lmax, nshell; the same
+ * precision, SIM_FP64 or SIM_FP32, and stream) run as one graph per call.
+ * The contexts must outlive the batch. */
 int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out);
 
 /* One realization per context: noise[i], fnl[i], aT[i], aE[i] as in
- * sim_forward with R = 1. */
+ * sim_forward with R = 1.  The batch runs in one of two graph-captured
+ * forms: grouped (one launch per stage and kernel class over all contexts,
+ * per-call pointers read from a device table) or branches (the contexts
+ * dealt by work onto 4 streams forked inside one graph, each running its
+ * contexts' passes back to back, so different stages of different contexts
+ * overlap; captured again when a pointer or f_NL changes).  The first call
+ * runs and times both and keeps the faster (the environment variable
+ * FNLSIM_BATCH_FORM=grouped or =branches, read by sim_batch_create, fixes the
+ * form instead); the results of the two are identical.  Asynchronous on the
+ * contexts' stream. */
 int sim_batch_forward(sim_batch *b, const void *const *noise, const double *fnl,
                       void *const *aT, void *const *aE);
+
+/* The form the batch chose (0 grouped, 1 branches, -1 before the first
+ * sim_batch_forward) and the first call's time of each form in ms
+ * (ms_grouped, ms_branches nullable). */
+int sim_batch_get_mode(const sim_batch *b, int *mode, double *ms_grouped, double *ms_branches);
 
 int sim_batch_destroy(sim_batch *b);
 

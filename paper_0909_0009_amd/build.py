@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfnlsim.so")
 SOURCES = [os.path.join(CSRC, "fnlsim.cpp"), os.path.join(CSRC, "kernels.hip"),
            os.path.join(CSRC, "quadrature.hip"), os.path.join(CSRC, "ksw.hip"),
-           os.path.join(CSRC, "tqu.hip")]
+           os.path.join(CSRC, "tqu.hip"), os.path.join(CSRC, "bf16.hip")]
 HEADERS = [os.path.join(CSRC, "internal.h"), os.path.join(CSRC, "quadrature.h"),
            os.path.join(CSRC, "device_common.h"),
            os.path.join(ROOT, "include", "fnlsim.h")]

@@ -493,4 +493,93 @@ __device__ __forceinline__ void fft_lds(C2 *buf, const Shape &sh, const GLB C2 *
     }
 }
 
+// Epilogue of the Legendre analysis (shared by the FP32/FP64 and the split
+// BF16 kernels, whose accumulators have the same 16x16 FP32/FP64 layout):
+// acc[f][par][cf] holds rows l = l0w + 2 (16 f + row(k4, r)) + par of column
+// colb + 16 cf.  MODE 0: radial partial sums part[ct][X][idx(l, m)] =
+// sum_s W^X_ls Phi_NL,lm(s) over the tile's shells, with the mean handling
+// at l = 0; MODE 1: per-shell Phi_NL into outphi; MODE 2 (reverse pass):
+// per-shell output plus sum_X W^X_ls abar^X_lm.
+template <typename T, int CF, int MODE, int NF>
+__device__ __forceinline__ void anal_epilogue(const Shape &sh, const typename Mt<T>::acc (&acc)[NF][2][CF],
+                                              int m, int l0w, int ct, int colb, int k4, int i16,
+                                              const double *__restrict__ W_in,
+                                              const double *__restrict__ mu_in,
+                                              double2 *__restrict__ part_in,
+                                              T *__restrict__ outphi_in,
+                                              const double2 *__restrict__ gT_in,
+                                              const double2 *__restrict__ gE_in)
+{
+    using M = Mt<T>;
+    auto *__restrict__ W = glb(W_in);
+    auto *__restrict__ mu = glb(mu_in);
+    auto *__restrict__ part = glb(part_in);
+    auto *__restrict__ outphi = glb(outphi_in);
+    auto *__restrict__ gT = glb(gT_in);
+    auto *__restrict__ gE = glb(gE_in);
+    const int L = sh.L, Cpad = sh.Cpad;
+    const long long rowm = mrow(L, m, m);
+    const int Npad = Cpad / 2;
+#pragma unroll
+    for (int f = 0; f < NF; f++)
+#pragma unroll
+        for (int par = 0; par < 2; par++)
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int l = l0w + 2 * (16 * f + M::row(k4, r)) + par;
+                const bool lok = l <= L;
+                double sT = 0.0, sE = 0.0;
+#pragma unroll
+                for (int cf = 0; cf < CF; cf++) {
+                    const int col = colb + 16 * cf;
+                    const int s = col >> 1;
+                    double v = (double)acc[f][par][cf][r];
+                    if (MODE == 2) {
+                        if (lok) {
+                            const long long id = lm_index(l, m);
+                            const double2 t = gload(gT + id), e = gload(gE + id);
+                            const double wt = W[(long long)l * Npad + s];
+                            const double we = W[(long long)(L + 1 + l) * Npad + s];
+                            v += (col & 1) ? (m == 0 ? 0.0 : wt * t.y + we * e.y)
+                                           : wt * t.x + we * e.x;
+                            if (m == 0 && (col & 1)) v = 0.0;
+                            outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
+                        }
+                        continue;
+                    }
+                    if (m == 0 && l == 0) {
+                        if (sh.mean_mode == 0)
+                            v = 0.0;
+                        else if ((col & 1) == 0)
+                            v -= mu[s];
+                    }
+                    if (MODE == 0) {
+                        if (lok) {
+                            sT += W[(long long)l * Npad + s] * v;
+                            sE += W[(long long)(L + 1 + l) * Npad + s] * v;
+                        }
+                    } else if (lok) {
+                        outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
+                    }
+                }
+                if (MODE == 0) {
+                    sT += __shfl_xor(sT, 2);
+                    sT += __shfl_xor(sT, 4);
+                    sT += __shfl_xor(sT, 8);
+                    sE += __shfl_xor(sE, 2);
+                    sE += __shfl_xor(sE, 4);
+                    sE += __shfl_xor(sE, 8);
+                    if (lok && i16 < 2) {
+                        const long long id = lm_index(l, m);
+                        GLB double *pT =
+                            reinterpret_cast<GLB double *>(part + ((long long)ct * 2) * sh.nlm + id);
+                        GLB double *pE =
+                            reinterpret_cast<GLB double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
+                        pT[i16] = (m == 0 && i16 == 1) ? 0.0 : sT;
+                        pE[i16] = (m == 0 && i16 == 1) ? 0.0 : sE;
+                    }
+                }
+            }
+}
+
 }  // namespace fnl

@@ -37,7 +37,8 @@ struct Shape {
     int radix[kMaxPasses];
     long long nlm;
     int mean_mode;
-    int fp32;     // 0: FP64 path, 1: FP32 matrix cores
+    int fp32;     // 0: FP64 path, 1: FP32 data (FP32 or split-BF16 matrix cores)
+    int npiece;   // 0: FP32/FP64 matrix cores; 2 or 3: BF16 pieces per operand (X3, X6)
     int lower;    // 1 if every F_l is lower triangular (contractions stop at the diagonal)
 };
 
@@ -100,6 +101,8 @@ struct Bufs {
     void *tw;          // [nphi] e^{-2 pi i q / nphi}
     double *mu;        // [Cpad/2] sqrt(4 pi) * ensemble <Phi_L^2>(r_s)
     void *phi;         // [nlm rows][Cpad] Phi_L (m-major)
+    void *phib;        // split BF16 paths: [nseedrow + 2][Cpad][2][npiece][16] BF16 pieces of
+                       // Phi_L per 32-l block of each m (two zero blocks at the end)
     void *G;           // [npair][L+1][Cpad][2] synthesis output, (E, O) interleaved
     void *F;           // [L+1][npair][Cpad][2] weighted ring spectra, (E, O) interleaved
     double2 *part;     // [nct][2][nlm] per-column-tile radial sums of Phi_NL
@@ -160,6 +163,12 @@ hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void
 hipError_t launch_noise(const Shape &sh, unsigned long long seed, void *out, hipStream_t s);
 hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
                         hipStream_t s);
+// split-BF16 forms of the Legendre kernels (bf16.hip; the generic launchers
+// dispatch to them when sh.npiece != 0)
+hipError_t launch_synth_bf(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
+                           hipStream_t s);
+hipError_t launch_anal_bf(const Shape &sh, const Bufs &b, const void *F_in, void *out_phi, int mode,
+                          hipStream_t s);
 // mode 0: square minus mean and forward transform into F; 1: write maps.
 hipError_t launch_ring(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
                        double *maps, int mode, hipStream_t s);

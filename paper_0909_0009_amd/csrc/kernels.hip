@@ -734,13 +734,7 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     auto *__restrict__ seed = glb(seed_in);
     auto *__restrict__ seedoff = glb(seedoff_in);
     auto *__restrict__ cmin = glb(cmin_in);
-    auto *__restrict__ W = glb(W_in);
-    auto *__restrict__ mu = glb(mu_in);
     auto *__restrict__ F = glb(F_in);
-    auto *__restrict__ part = glb(part_in);
-    auto *__restrict__ outphi = glb(outphi_in);
-    auto *__restrict__ gT = glb(gT_in);
-    auto *__restrict__ gE = glb(gE_in);
     using M = Mt<T>;
     constexpr int RW = anal_rw<T>();
     constexpr int NF = RW / 32;
@@ -765,7 +759,6 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     const int l0w = m + lt * RW;
     const int lh = l0w + half * (RW / 2);  // first recurrence row of this lane
     const bool hact = lh <= L;
-    const long long rowm = mrow(L, m, m);
     const long long srow = (long long)seedoff[m] + (hact ? (lh - m) / kSeedStride : 0);
     // rows past l = L take the zero padding of m's coefficient block
     for (int r = lane; r < RW; r += 64) cab[r] = gload(cm_row + (l0w - m) + r);
@@ -854,67 +847,8 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
         __syncthreads();
     }
 
-    const int Npad = Cpad / 2;
-#pragma unroll
-    for (int f = 0; f < NF; f++)
-#pragma unroll
-        for (int par = 0; par < 2; par++)
-#pragma unroll
-            for (int r = 0; r < 4; r++) {
-                const int l = l0w + 2 * (16 * f + M::row(k4, r)) + par;
-                const bool lok = l <= L;
-                double sT = 0.0, sE = 0.0;
-#pragma unroll
-                for (int cf = 0; cf < CF; cf++) {
-                    const int col = colb + 16 * cf;
-                    const int s = col >> 1;
-                    double v = (double)acc[f][par][cf][r];
-                    if (MODE == 2) {
-                        if (lok) {
-                            const long long id = lm_index(l, m);
-                            const double2 t = gload(gT + id), e = gload(gE + id);
-                            const double wt = W[(long long)l * Npad + s];
-                            const double we = W[(long long)(L + 1 + l) * Npad + s];
-                            v += (col & 1) ? (m == 0 ? 0.0 : wt * t.y + we * e.y)
-                                           : wt * t.x + we * e.x;
-                            if (m == 0 && (col & 1)) v = 0.0;
-                            outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
-                        }
-                        continue;
-                    }
-                    if (m == 0 && l == 0) {
-                        if (sh.mean_mode == 0)
-                            v = 0.0;
-                        else if ((col & 1) == 0)
-                            v -= mu[s];
-                    }
-                    if (MODE == 0) {
-                        if (lok) {
-                            sT += W[(long long)l * Npad + s] * v;
-                            sE += W[(long long)(L + 1 + l) * Npad + s] * v;
-                        }
-                    } else if (lok) {
-                        outphi[(rowm + (l - m)) * Cpad + col] = (T)v;
-                    }
-                }
-                if (MODE == 0) {
-                    sT += __shfl_xor(sT, 2);
-                    sT += __shfl_xor(sT, 4);
-                    sT += __shfl_xor(sT, 8);
-                    sE += __shfl_xor(sE, 2);
-                    sE += __shfl_xor(sE, 4);
-                    sE += __shfl_xor(sE, 8);
-                    if (lok && i16 < 2) {
-                        const long long id = lm_index(l, m);
-                        GLB double *pT =
-                            reinterpret_cast<GLB double *>(part + ((long long)ct * 2) * sh.nlm + id);
-                        GLB double *pE =
-                            reinterpret_cast<GLB double *>(part + ((long long)ct * 2 + 1) * sh.nlm + id);
-                        pT[i16] = (m == 0 && i16 == 1) ? 0.0 : sT;
-                        pE[i16] = (m == 0 && i16 == 1) ? 0.0 : sE;
-                    }
-                }
-            }
+    anal_epilogue<T, CF, MODE, NF>(sh, acc, m, l0w, ct, colb, k4, i16, W_in, mu_in, part_in, outphi_in,
+                                   gT_in, gE_in);
 }
 
 // waves per SIMD the analysis register budget is held to
@@ -1508,6 +1442,7 @@ static void synth_cf(const Shape &sh, const Bufs &b, const void *phi, void *G, h
 hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void *G_out,
                         hipStream_t s)
 {
+    if (sh.npiece) return launch_synth_bf(sh, b, phi_in, G_out, s);
     if (sh.fp32)
         synth_cf<float>(sh, b, phi_in, G_out, s);
     else
@@ -1598,6 +1533,10 @@ static void anal_cf(const Shape &sh, const Bufs &b, const void *F, void *out, in
 hipError_t launch_anal(const Shape &sh, const Bufs &b, const void *F_in, void *out_phi, int mode,
                        hipStream_t s, const double2 *gT, const double2 *gE)
 {
+    if (sh.npiece) {
+        if (mode == 2) return hipErrorInvalidValue;  // the reverse pass rejects split-BF16 contexts
+        return launch_anal_bf(sh, b, F_in, out_phi, mode, s);
+    }
     if (sh.fp32)
         anal_cf<float>(sh, b, F_in, out_phi, mode, gT, gE, s);
     else

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfnlsim.so")
 
 SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE = 0, -1, -2, -3, -4
-SIM_FP64, SIM_FP32 = 0, 1
+SIM_FP64, SIM_FP32, SIM_BF16X3, SIM_BF16X6 = 0, 1, 2, 3
 SIM_MEAN_SAMPLE, SIM_MEAN_ENSEMBLE = 0, 1
 SIM_STAGE_FILTER, SIM_STAGE_NONLIN, SIM_STAGE_MAPS = 1, 2, 3
 
@@ -25,11 +25,12 @@ EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_ba
            "sim_backward_seeded", "sim_quadrature_design", "sim_quadrature_design_noalloc",
            "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
-           "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_destroy",
+           "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_get_mode",
+           "sim_batch_destroy",
            "sim_ksw_init", "sim_ksw_cubic", "sim_tqu_maps",
            "sim_destroy", "sim_last_error")
 
-_PRECISION = {"fp64": SIM_FP64, "fp32": SIM_FP32}
+_PRECISION = {"fp64": SIM_FP64, "fp32": SIM_FP32, "bf16x3": SIM_BF16X3, "bf16x6": SIM_BF16X6}
 _MEAN = {"sample": SIM_MEAN_SAMPLE, "ensemble": SIM_MEAN_ENSEMBLE}
 
 
@@ -95,6 +96,8 @@ def lib():
         L.sim_batch_create.restype = ip
         L.sim_batch_forward.argtypes = [vp, vp, vp, vp, vp]
         L.sim_batch_forward.restype = ip
+        L.sim_batch_get_mode.argtypes = [vp, vp, vp, vp]
+        L.sim_batch_get_mode.restype = ip
         L.sim_batch_destroy.argtypes = [vp]
         L.sim_batch_destroy.restype = ip
         L.sim_ksw_init.argtypes = [ctypes.POINTER(vp), ip, ip, vp, vp, vp, vp, vp,
@@ -450,6 +453,16 @@ class Batch:
         f = np.ascontiguousarray(fnls, dtype=np.float64)
         _check(lib().sim_batch_forward(self._h, nz, f.ctypes.data, aT, aE), None)
         return outs
+
+    def mode(self):
+        """(form, ms_grouped, ms_branches): the form the first call chose
+        (0 grouped, 1 branches, -1 before it) and its timing of each."""
+        m = ctypes.c_int(0)
+        g = ctypes.c_double(0.0)
+        b = ctypes.c_double(0.0)
+        _check(lib().sim_batch_get_mode(self._h, ctypes.byref(m), ctypes.byref(g), ctypes.byref(b)),
+               None)
+        return m.value, g.value, b.value
 
     def close(self):
         if getattr(self, "_h", None):

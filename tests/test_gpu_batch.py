@@ -47,8 +47,13 @@ def _run_batch(fs, h, noises, fnls, outs):
     assert rc == 0
 
 
+@pytest.mark.parametrize("form", ["grouped", "branches", "auto"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batch_equals_sequential(fs, precision):
+def test_batch_equals_sequential(fs, precision, form, monkeypatch):
+    if form != "auto":
+        monkeypatch.setenv("FNLSIM_BATCH_FORM", form)
+    else:
+        monkeypatch.delenv("FNLSIM_BATCH_FORM", raising=False)
     import torch
     dt = torch.complex128 if precision == "fp64" else torch.complex64
     sims, probs = [], []
@@ -76,9 +81,21 @@ def test_batch_equals_sequential(fs, precision):
                 L = MIX[i][0]
                 assert_close(outs[i][0].cpu().numpy(), rT.cpu().numpy(), L, 1e-13, f"batch aT {i}")
                 assert_close(outs[i][1].cpu().numpy(), rE.cpu().numpy(), L, 1e-13, f"batch aE {i}")
-            print(f"call {call}: {exact}/{len(sims)} realizations bitwise equal", flush=True)
+            print(f"{form} call {call}: {exact}/{len(sims)} realizations bitwise equal", flush=True)
+            assert exact == len(sims)
+        m = ctypes.c_int(-2)
+        fs.lib().sim_batch_get_mode(h, ctypes.byref(m), None, None)
+        assert m.value == {"grouped": 0, "branches": 1}.get(form, m.value) and m.value in (0, 1)
     finally:
         fs.lib().sim_batch_destroy(h)
+
+
+def test_batch_rejects_a_repeated_context(fs):
+    p = inputs.problem(16, 5)
+    a = fs.Simulator(16, p["r"], p["w"], p["filter"], p["alpha"], p["beta"])
+    arr = (ctypes.c_void_p * 2)(a.handle.value, a.handle.value)
+    h = ctypes.c_void_p()
+    assert fs.lib().sim_batch_create(arr, 2, ctypes.byref(h)) == fs.SIM_EINVAL
 
 
 def test_batch_rejects_mixed_precision(fs):
