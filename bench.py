@@ -27,6 +27,7 @@ PEAK = {  # MI355X published dense peaks
     "hbm_GBs": 8000.0,
     "fp64_mfma_TFs": 78.6,
     "fp32_mfma_TFs": 157.3,
+    "bf16_mfma_TFs": 2500.0,
 }
 
 
@@ -56,7 +57,7 @@ def stage_work(sim, stage, precision):
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
-    for f in ("kernels.hip", "internal.h"):
+    for f in ("kernels.hip", "internal.h", "device_common.h"):
         with open(os.path.join(ROOT, "paper_0909_0009_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -125,10 +126,38 @@ def time_path(torch, fnlsim, p, cfg, noise_np, precision, steps, warmup):
     stages = sim.profile_read()
     sim.profile(False)
     aT, aE = out
+    # the non-linear parts alone (outside the timed region): they carry the
+    # error of the matrix-core transforms, which the linear part hides
+    nl = sim.forward(noise, cfg["fnl"], want_nl=True)
     res = dict(ms=ms, stages=stages, aT=aT.cpu().numpy().ravel(), aE=aE.cpu().numpy().ravel(),
+               aT_nl=nl[2].cpu().numpy().ravel(), aE_nl=nl[3].cpu().numpy().ravel(),
                sim=sim, ws=sim.workspace_bytes)
-    del noise
+    del noise, nl
     return res
+
+
+def split_bf16_leg(r, ref, precision, L):
+    """Timing and error of a split-BF16 form of the Legendre transforms.
+    The matrix cores issue nprod BF16 products per FP32 product; the rate
+    of those products is set against the dense BF16 peak."""
+    nprod = 3 if precision == "bf16x3" else 6
+    sim = r["sim"]
+    legs = {}
+    for st in ("synth", "anal"):
+        tot, n = r["stages"][st]
+        avg_s = tot / max(n, 1) / 1e3
+        _, work, _ = stage_work(sim, st, "fp32")
+        legs[st] = {"avg_launch_ms": round(avg_s * 1e3, 4),
+                    "algorithmic_TFs": round(work / avg_s / 1e12, 2),
+                    "bf16_products_TFs": round(nprod * work / avg_s / 1e12, 2),
+                    "frac_of_bf16_peak": round(nprod * work / avg_s / 1e12 / PEAK["bf16_mfma_TFs"], 4)}
+    err_nl = None
+    if ref is not None:
+        err_nl = max(per_l_rel_err(r["aT_nl"], ref["aT_nl"], L),
+                     per_l_rel_err(r["aE_nl"], ref["aE_nl"], L))
+    return {"value": round(1000.0 / r["ms"], 4), "ms_per_step": round(r["ms"], 4),
+            "stages_ms": {k: round(v[0] / max(v[1], 1), 4) for k, v in r["stages"].items()},
+            "legendre": legs, "nl_max_rel_err_vs_fp64": err_nl}
 
 
 def time_seeded(torch, sim, cfg, steps, warmup):
@@ -470,6 +499,8 @@ def main():
                     help="skip the radial-quadrature design leg")
     ap.add_argument("--no-seeded", action="store_true",
                     help="skip the counter-based-noise forward leg")
+    ap.add_argument("--no-split-bf16", action="store_true",
+                    help="skip the split-BF16 forms of the Legendre transforms")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the uneven 32-realization batch leg")
     args = ap.parse_args()
@@ -515,6 +546,7 @@ def main():
     torch.cuda.empty_cache()
     fp64 = None
     err = None
+    err_nl = None
     if not args.fp32_only:
         r64 = time_path(torch, fnlsim, p, cfg, noise_np, "fp64", args.steps, args.warmup)
         log(f"fp64: {r64['ms']:.3f} ms/step")
@@ -529,8 +561,20 @@ def main():
         # error of the mixed path against the FP64 GPU path (which matches the
         # FP64 oracle to <= 1e-10 at this workload)
         err = max(per_l_rel_err(r32["aT"], r64["aT"], L), per_l_rel_err(r32["aE"], r64["aE"], L))
+        err_nl = max(per_l_rel_err(r32["aT_nl"], r64["aT_nl"], L),
+                     per_l_rel_err(r32["aE_nl"], r64["aE_nl"], L))
         r64["sim"].close()
         torch.cuda.empty_cache()
+    split = None
+    if not args.no_split_bf16:
+        split = {}
+        for pr in ("bf16x3", "bf16x6"):
+            rb = time_path(torch, fnlsim, p, cfg, noise_np, pr, args.steps, args.warmup)
+            split[pr] = split_bf16_leg(rb, r64 if fp64 is not None else None, pr, L)
+            rb["sim"].close()
+            del rb
+            torch.cuda.empty_cache()
+        log(f"split bf16: {split}")
 
     grad = None
     if not args.no_grad:
@@ -587,6 +631,8 @@ def main():
         "roofline": roof,
         "fp64": fp64,
         "mixed_vs_fp64_max_rel_err": err,
+        "mixed_vs_fp64_nl_max_rel_err": err_nl,
+        "split_bf16": split,
         "seeded": seeded,
         "ksw_cubic_statistic": ksw,
         "tqu_maps": tqu,

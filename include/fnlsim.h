@@ -19,9 +19,11 @@
  * Besides that forward pass it offers the reverse pass (sim_backward), the
  * same passes with the noise regenerated from a seed instead of stored
  * (sim_noise, sim_forward_seeded, sim_backward_seeded; Sect. 3's memory
- * remark), grouped launches over uneven problems (sim_batch_*), and the
+ * remark), launches over several uneven problems at once (sim_batch_*), the
  * greedy design of the radial quadrature nodes and weights
- * (sim_quadrature_design; Sect. 3).
+ * (sim_quadrature_design; Sect. 3), the T, Q, U maps of generated
+ * coefficients (sim_tqu_maps; Sect. 3) and the cubic KSW statistic of
+ * Sect. 4 (sim_ksw_init, sim_ksw_cubic).
  *
  * Conventions
  *   - lmax = L, nshell = N, n_lm = (L+1)(L+2)/2.

@@ -406,8 +406,26 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     sh.L = L;
     sh.N = N;
     sh.C = 2 * N;
+    const int npiece = o.precision == SIM_BF16X3 ? 2 : o.precision == SIM_BF16X6 ? 3 : 0;
     if (force_cf) {
         sh.CF = force_cf;
+    } else if (npiece) {
+        // every column tile repeats the Legendre recurrence and its splits,
+        // so the split-BF16 kernels take the widest tile that pads the
+        // columns by at most an eighth.  With two pieces the 80-column
+        // synthesis tile no longer fits its accumulators in the VGPRs and
+        // runs 1.5x slower than the 64-column one (measured at lmax 1024,
+        // 400 columns); with three pieces the 80-column tile is still the
+        // fastest.
+        const int cf_max = npiece == 2 ? 4 : 5;
+        sh.CF = 1;
+        for (int cf = cf_max; cf >= 1; cf--) {
+            const int ct = 16 * cf;
+            if (8 * (((sh.C + ct - 1) / ct) * ct - sh.C) <= sh.C || cf == 1) {
+                sh.CF = cf;
+                break;
+            }
+        }
     } else {
         int best = 1, bestpad = 1 << 30;
         for (int cf = 5; cf >= 1; cf--) {
