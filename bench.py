@@ -76,8 +76,9 @@ def measured_traffic(stage, precision):
         return None
     T = "float" if precision == "fp32" else "double"
     pat = re.compile(rf"^k_{stage}<{T}[,>]")
-    # the stored-noise instantiation (", true>" marks the seeded filter)
-    hits = [v for k, v in rec["kernels"].items() if pat.match(k) and not k.endswith(", true>")]
+    # the filter's stored-noise instantiation (", true>" marks the seeded one)
+    hits = [v for k, v in rec["kernels"].items()
+            if pat.match(k) and not (stage == "filter" and k.endswith(", true>"))]
     return round(hits[0]["traffic_bytes"]) if len(hits) == 1 else None
 
 
