@@ -102,8 +102,13 @@ typedef struct {
     int max_batch;  /* reserved; 0                                                 */
     void *stream;   /* hipStream_t for every launch; NULL = default stream         */
     int tune;       /* 0: column tile of 16 CF columns with CF in 1..5 chosen to
-                       minimise padding; 1: time one forward pass (zero noise)
-                       for every CF at set-up and keep the fastest              */
+                       minimise padding, 2 shells per ring-stage block with
+                       FP32 data (1 with FP64); 1: time one forward pass (zero
+                       noise) for every CF at set-up and keep the fastest, then
+                       with FP32 data time 1 shell per ring block against 2
+                       and keep the faster (sim_info reports both choices)     */
+    int ring_shells; /* 0: as above; 1 or 2: shells per ring-stage block, fixed
+                        (FP32 data; SIM_FP64 takes 1 only), not tuned          */
 } sim_opts;
 
 /* Read-only facts about a context. */
@@ -112,6 +117,7 @@ typedef struct {
     long long n_lm;
     long long workspace_bytes;  /* device memory owned by the context          */
     int col_tile;               /* columns per matrix-core tile (16 CF)        */
+    int ring_shells;            /* shells per block of the ring FFT stage      */
 } sim_info;
 
 /* Create a context for band limit lmax and nshell radial nodes.

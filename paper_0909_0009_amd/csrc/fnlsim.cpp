@@ -383,6 +383,10 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     if (o.mean_mode != SIM_MEAN_SAMPLE && o.mean_mode != SIM_MEAN_ENSEMBLE)
         return fail(nullptr, SIM_EINVAL, "unknown mean_mode %d", o.mean_mode);
     if (o.max_batch < 0) return fail(nullptr, SIM_EINVAL, "max_batch < 0");
+    if (o.ring_shells < 0 || o.ring_shells > 2)
+        return fail(nullptr, SIM_EINVAL, "ring_shells %d is not 0, 1 or 2", o.ring_shells);
+    if (o.ring_shells == 2 && o.precision == SIM_FP64)
+        return fail(nullptr, SIM_EINVAL, "SIM_FP64 runs 1 shell per ring block");
     if (!all_finite(r, Nk) || !all_finite(w, Nk))
         return fail(nullptr, SIM_EINVAL, "r or w has a non-finite value");
     if (ksw) {
@@ -452,6 +456,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     sh.mean_mode = o.mean_mode;
     sh.fp32 = o.precision != SIM_FP64;
     sh.npiece = o.precision == SIM_BF16X3 ? 2 : o.precision == SIM_BF16X6 ? 3 : 0;
+    sh.rs = o.ring_shells ? o.ring_shells : fnl::ring_shells(sh.fp32);
     sh.lower = ksw ? 0 : 1;
     for (int l = 0; l <= L && sh.lower; l++)
         for (int i = 0; i < N && sh.lower; i++)
@@ -708,7 +713,9 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
     if (opts) o = *opts;
     if (o.tune != 0 && o.tune != 1) return fail(nullptr, SIM_EINVAL, "tune must be 0 or 1");
     if (!o.tune) return init_ctx(out, lmax, nshell, r, w, filter, alpha, beta, o, 0);
-    // column-tile autotuner: one context per CF, the fastest is kept
+    // autotuner: one context per CF, the fastest is kept; then, with FP32
+    // data, the ring stage's shells per block (a launch shape only, so it is
+    // timed on that context in place)
     sim_ctx *best = nullptr;
     double best_ms = 0.0;
     for (int cf = 5; cf >= 1; cf--) {
@@ -731,6 +738,16 @@ int sim_init(sim_ctx **out, int lmax, int nshell, const double *r, const double 
         } else {
             sim_destroy(c);
         }
+    }
+    if (best->sh.fp32 && !o.ring_shells) {
+        const int rs0 = best->sh.rs;
+        best->sh.rs = rs0 == 1 ? 2 : 1;
+        const double ms = time_forward(best);
+        if (ms < 0.0) {
+            sim_destroy(best);
+            return fail(nullptr, SIM_EDEVICE, "ring-block tuning: a timed forward pass failed");
+        }
+        if (ms >= best_ms) best->sh.rs = rs0;
     }
     *out = best;
     return SIM_OK;
@@ -765,6 +782,7 @@ int sim_get_info(const sim_ctx *c, sim_info *info)
     info->n_lm = c->sh.nlm;
     info->workspace_bytes = c->ws_bytes;
     info->col_tile = c->sh.CT;
+    info->ring_shells = c->sh.rs;
     return SIM_OK;
 }
 

@@ -40,12 +40,13 @@ struct Shape {
     int fp32;     // 0: FP64 path, 1: FP32 data (FP32 or split-BF16 matrix cores)
     int npiece;   // 0: FP32/FP64 matrix cores; 2 or 3: BF16 pieces per operand (X3, X6)
     int lower;    // 1 if every F_l is lower triangular (contractions stop at the diagonal)
+    int rs;       // shells per forward ring block: 1 or 2 (FP32 data), 1 (FP64)
 };
 
 // Elements of one ring buffer in LDS: n values at j + j/32, plus one slot.
 __host__ __device__ constexpr int ring_pad(int n) { return n + (n >> 5) + 1; }
 constexpr size_t kMaxLds = 163840;  // LDS bytes a workgroup may allocate
-// Shells per forward ring block (256 threads each) in FP32 / FP64.
+// Default shells per forward ring block (256 threads each) in FP32 / FP64.
 constexpr int kRingShellsF32 = 2;
 constexpr int kRingShellsF64 = 1;
 inline int ring_shells(int fp32) { return fp32 ? kRingShellsF32 : kRingShellsF64; }

@@ -682,16 +682,19 @@ __device__ __forceinline__ void body_ring(const Shape &sh, const double *__restr
     }
 }
 
-// shells per ring block: 2 in FP32 (512 threads), 1 in FP64
+// default shells per ring block: 2 in FP32 (512 threads), 1 in FP64 (the
+// grouped batch kernels always use these)
 template <typename T> constexpr int ring_s() { return sizeof(T) == 4 ? kRingShellsF32 : kRingShellsF64; }
 
-template <typename T, int NMAX, bool PLANNED>
-__global__ __launch_bounds__(256 * ring_s<T>()) void k_ring(Shape sh, const double *__restrict__ wq,
-                                                            const typename Mt<T>::c2 *__restrict__ tw,
-                                                            const T *__restrict__ G, T *__restrict__ F,
-                                                            double *__restrict__ maps, int mode)
+// S shells per block (Shape::rs): the single-context launches take the
+// context's choice, 1 or 2 in FP32
+template <typename T, int NMAX, bool PLANNED, int S>
+__global__ __launch_bounds__(256 * S) void k_ring(Shape sh, const double *__restrict__ wq,
+                                                  const typename Mt<T>::c2 *__restrict__ tw,
+                                                  const T *__restrict__ G, T *__restrict__ F,
+                                                  double *__restrict__ maps, int mode)
 {
-    body_ring<T, NMAX, ring_s<T>(), PLANNED>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
+    body_ring<T, NMAX, S, PLANNED>(sh, wq, tw, G, F, maps, mode, blockIdx.x);
 }
 
 // --------------------------------------------------------- Legendre analysis
@@ -1453,21 +1456,32 @@ hipError_t launch_synth(const Shape &sh, const Bufs &b, const void *phi_in, void
 // Smallest supported maximum ring length covering n.
 static int nmax_for(int n) { return ring_bucket(n); }
 
-template <typename T, int NMAX, bool PLANNED>
-static hipError_t ring_t(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
-                         double *maps, int mode, hipStream_t s)
+template <typename T, int NMAX, bool PLANNED, int S>
+static hipError_t ring_ts(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                          double *maps, int mode, hipStream_t s)
 {
     using C2 = typename Mt<T>::c2;
-    constexpr int S = ring_s<T>();
     const long long nblk = (long long)sh.npair * ((sh.N + S - 1) / S);
     dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
     const size_t lds = S * sizeof(C2) * ring_pad(sh.nphi);
     if (lds > 65536)
-        (void)hipFuncSetAttribute((const void *)k_ring<T, NMAX, PLANNED>,
+        (void)hipFuncSetAttribute((const void *)k_ring<T, NMAX, PLANNED, S>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL((k_ring<T, NMAX, PLANNED>), grid, dim3(256 * S), lds, s, sh, b.wq,
+    hipLaunchKernelGGL((k_ring<T, NMAX, PLANNED, S>), grid, dim3(256 * S), lds, s, sh, b.wq,
                        (const C2 *)b.tw, (const T *)G_in, (T *)F_out, maps, mode);
     return hipGetLastError();
+}
+
+template <typename T, int NMAX, bool PLANNED>
+static hipError_t ring_t(const Shape &sh, const Bufs &b, const void *G_in, void *F_out,
+                         double *maps, int mode, hipStream_t s)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (sh.rs == 1) return ring_ts<T, NMAX, PLANNED, 1>(sh, b, G_in, F_out, maps, mode, s);
+        return ring_ts<T, NMAX, PLANNED, 2>(sh, b, G_in, F_out, maps, mode, s);
+    } else {
+        return ring_ts<T, NMAX, PLANNED, 1>(sh, b, G_in, F_out, maps, mode, s);
+    }
 }
 
 template <typename T, int NMAX>

@@ -43,14 +43,15 @@ class SimError(RuntimeError):
 class _Opts(ctypes.Structure):
     _fields_ = [("n_ring", ctypes.c_int), ("n_phi", ctypes.c_int), ("precision", ctypes.c_int),
                 ("mean_mode", ctypes.c_int), ("max_batch", ctypes.c_int),
-                ("stream", ctypes.c_void_p), ("tune", ctypes.c_int)]
+                ("stream", ctypes.c_void_p), ("tune", ctypes.c_int), ("ring_shells", ctypes.c_int)]
 
 
 class _Info(ctypes.Structure):
     _fields_ = [("lmax", ctypes.c_int), ("nshell", ctypes.c_int), ("n_ring", ctypes.c_int),
                 ("n_phi", ctypes.c_int), ("n_pair", ctypes.c_int), ("precision", ctypes.c_int),
                 ("mean_mode", ctypes.c_int), ("n_lm", ctypes.c_longlong),
-                ("workspace_bytes", ctypes.c_longlong), ("col_tile", ctypes.c_int)]
+                ("workspace_bytes", ctypes.c_longlong), ("col_tile", ctypes.c_int),
+                ("ring_shells", ctypes.c_int)]
 
 
 _lib = None
@@ -193,7 +194,7 @@ class Simulator:
     """One context of the map generator (see include/fnlsim.h)."""
 
     def __init__(self, lmax, r, w, filt, alpha, beta, n_ring=0, n_phi=0, precision="fp64",
-                 mean="sample", stream=None, tune=False):
+                 mean="sample", stream=None, tune=False, ring_shells=0):
         self.lmax = int(lmax)
         r, w, filt, alpha, beta = map(_f64, (r, w, filt, alpha, beta))
         self.nshell = int(r.shape[0])
@@ -206,7 +207,8 @@ class Simulator:
             stream = torch.cuda.current_stream().cuda_stream
         self.stream = stream
         opts = _Opts(int(n_ring), int(n_phi), _PRECISION[precision], _MEAN[mean], 0,
-                     ctypes.c_void_p(stream) if stream else None, 1 if tune else 0)
+                     ctypes.c_void_p(stream) if stream else None, 1 if tune else 0,
+                     int(ring_shells))
         h = ctypes.c_void_p()
         rc = lib().sim_init(ctypes.byref(h), L, N, r.ctypes.data, w.ctypes.data,
                             filt.ctypes.data, alpha.ctypes.data, beta.ctypes.data,
@@ -219,6 +221,7 @@ class Simulator:
         self.n_lm = int(info.n_lm)
         self.workspace_bytes = int(info.workspace_bytes)
         self.col_tile = int(info.col_tile)
+        self.ring_shells = int(info.ring_shells)
 
     def close(self):
         if getattr(self, "_h", None):

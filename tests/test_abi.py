@@ -56,7 +56,8 @@ def _init(fs, L, N, r, w, F, a, b, opts=None):
 
 @pytest.mark.parametrize("case", ["lmax0", "nshell0", "null_filter", "nan_filter", "inf_r",
                                   "few_rings", "short_ring", "bad_radix", "big_phi",
-                                  "bad_precision", "bad_mean", "bad_tune"])
+                                  "bad_precision", "bad_mean", "bad_tune", "bad_ring_shells",
+                                  "fp64_two_ring_shells"])
 def test_init_rejects_bad_arguments_without_device(fs, case):
     L, N = 4, 3
     r, w, F, a, b = _args(L, N)
@@ -85,6 +86,11 @@ def test_init_rejects_bad_arguments_without_device(fs, case):
         opts.mean_mode = 3
     elif case == "bad_tune":
         opts.tune = 2
+    elif case == "bad_ring_shells":
+        opts.precision = fs.SIM_FP32
+        opts.ring_shells = 3
+    elif case == "fp64_two_ring_shells":
+        opts.ring_shells = 2
     rc, h = _init(fs, L, N, r, w, F, a, b, opts)
     assert rc == fs.SIM_EINVAL
     assert not h.value

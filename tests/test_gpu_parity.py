@@ -204,6 +204,22 @@ def test_dense_filter(fs, orc, precision):
     _check_all(got, ref, L, TOL[precision], f"dense filter {precision}")
 
 
+@pytest.mark.parametrize("L,N,nphi", [(40, 33, 0), (256, 64, 0), (64, 5, 200)])
+@pytest.mark.parametrize("rs", [1, 2])
+def test_fp32_ring_shells_per_block(fs, orc, L, N, nphi, rs):
+    """Both ring-stage block shapes of the FP32 data path (1 or 2 shells per
+    block, the launch shape the autotuner chooses between) give the oracle's
+    result: planned and run-time FFT lengths, an odd shell count."""
+    p = _problem(L, N)
+    sim = fs.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"], n_phi=nphi,
+                       precision="fp32", ring_shells=rs)
+    assert sim.ring_shells == rs
+    noise = inputs.noise(L, N, 91).astype(np.complex64).astype(np.complex128)
+    got = sim.forward(_dev(noise, "fp32"), 60.0, want_nl=True)
+    ref = _oracle(orc, p, L, nphi=nphi or None).forward(noise, 60.0)
+    _check_all(got, ref, L, TOL["fp32"], f"L={L} N={N} nphi={nphi} ring shells {rs}")
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_tuned_column_tile(fs, orc, precision):
     """The set-up autotuner (one context per column tile, fastest kept) gives
@@ -213,6 +229,7 @@ def test_tuned_column_tile(fs, orc, precision):
     tuned = _sim(fs, p, L, precision, tune=True)
     plain = _sim(fs, p, L, precision)
     assert tuned.col_tile in (16, 32, 48, 64, 80) and plain.col_tile in (16, 32, 48, 64, 80)
+    assert tuned.ring_shells in ((1, 2) if precision == "fp32" else (1,))
     noise = inputs.noise(L, N, 77)
     if precision == "fp32":
         noise = noise.astype(np.complex64).astype(np.complex128)
