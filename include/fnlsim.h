@@ -249,8 +249,7 @@ int sim_quadrature_design_noalloc(const double *cov, const double *a, int P, int
  *            (the grid integrates A B^2 exactly; with n_phi = 3L the one
  *            aliased term is removed); mean_mode and tune must be 0
  * Host arrays, FP64.  SIM_EINVAL for bad sizes, null pointers, non-finite
- * values, Nk > 2048, or an n_phi whose two rings do not fit in LDS at the
- * precision.  The two filtered maps of every node run through the same
+ * values or Nk > 2048.  The two filtered maps of every node run through the same
  * Legendre synthesis as the generator (FP32 matrix cores in SIM_FP32); the
  * sky and radial sums are FP64.
  * sim_ksw_cubic computes S_prim for R realizations:

@@ -395,8 +395,9 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             return fail(nullptr, SIM_EINVAL, "alpha or beta has a non-finite value");
         if (!all_finite(ksw->cinv, (size_t)4 * (L + 1)))
             return fail(nullptr, SIM_EINVAL, "cinv has a non-finite value");
+        // the statistic's ring stage holds one ring in LDS
         const size_t elem = o.precision == SIM_FP32 ? sizeof(float2) : sizeof(double2);
-        if (2 * elem * (size_t)fnl::ring_pad(nphi) > fnl::kMaxLds)
+        if (elem * (size_t)fnl::ring_pad(nphi) > fnl::kMaxLds)
             return fail(nullptr, SIM_EINVAL, "n_phi %d is too long for the cubic statistic at this precision",
                         nphi);
     } else {

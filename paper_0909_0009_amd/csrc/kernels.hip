@@ -226,10 +226,18 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
                 }
             }
         };
-        T v[8];
+        // FP32 stored-noise kernel: the noise rows load two chunks ahead (the
+        // last chunks of a triangular F have too little matrix work to cover
+        // one chunk's load); the FP64 and seeded kernels have no registers to
+        // spare and stage one chunk ahead
+        constexpr bool N2 = sizeof(T) == 4 && !SEEDED;
+        T v[8], v2[N2 ? 8 : 1];
         stage_load(0, v);
         if (u0 == 0) radial_acc(0, v);  // the first round stages every row
         stage_store(0, v);
+        if constexpr (N2) {
+            if (nchunk > 1) stage_load(32, v2);
+        }
         load_a(0, af);
         __syncthreads();
         for (int c = 0; c < nchunk; c++) {
@@ -237,7 +245,9 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
             // load; the next chunk's F^T fragments load after the MFMAs
             const int buf = c & 1;
             const bool more = c + 1 < nchunk;
-            if (more) {
+            if constexpr (N2) {
+                if (c + 2 < nchunk) stage_load(32 * (c + 2), v);
+            } else if (more) {
                 stage_load(32 * (c + 1), v);
                 if (u0 == 0) radial_acc(32 * (c + 1), v);
             }
@@ -260,7 +270,13 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
                 }
             }
             if (more) {
-                stage_store(buf ^ 1, v);
+                if constexpr (N2) {
+                    stage_store(buf ^ 1, v2);
+#pragma unroll
+                    for (int e = 0; e < 8; e++) v2[e] = v[e];
+                } else {
+                    stage_store(buf ^ 1, v);
+                }
                 load_a(c + 1, af);
             }
             __syncthreads();

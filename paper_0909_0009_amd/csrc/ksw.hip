@@ -78,9 +78,19 @@ __device__ __forceinline__ void ksw_load_ring(const Shape &sh, const T *__restri
 
 // Block = (ring pair p, node k), 256 threads.  Both rings of the pair travel
 // as one complex sequence per map, so after the inverse FFTs pixel j of the
-// north ring is (Re a, Re b) and of the south ring (Im a, Im b).  With
-// n = 3L the pixel sum of A B^2 also picks up the modes +-3L of the product,
+// north ring is (Re a, Re b) and of the south ring (Im a, Im b).  One LDS
+// ring serves both maps: A is transformed first and each thread keeps its
+// pixels of A in registers while the ring is reused for B (two rings per
+// block would hold the FP64 kernel to one block per CU).  With n = 3L the
+// pixel sum of A B^2 also picks up the modes +-3L of the product,
 // 2 n Re(A_L B_L^2) per ring, which are removed.
+template <int NMAX, bool PLANNED> constexpr int ksw_pix()
+{
+    // pixels per thread: the planned lengths of a bucket are 3/4 of it
+    // (all of it for 1024), the run-time plans up to all of it
+    return PLANNED && NMAX != 1024 ? 3 * NMAX / 4 / 256 : NMAX / 256;
+}
+
 template <typename T, int NMAX, bool PLANNED>
 __global__ __launch_bounds__(256) void k_ksw_ring(Shape sh, const double *__restrict__ wq,
                                                   const typename Mt<T>::c2 *__restrict__ tw,
@@ -91,7 +101,6 @@ __global__ __launch_bounds__(256) void k_ksw_ring(Shape sh, const double *__rest
     extern __shared__ unsigned char smem_raw[];
     const int L = sh.L, n = sh.nphi, Nk = sh.N / 2;
     C2 *b1 = reinterpret_cast<C2 *>(smem_raw);
-    C2 *b2 = b1 + ring_pad(n);
     __shared__ double red[256];
     const int nblk = sh.npair * Nk;
     const int nslot = (nblk + 7) / 8;
@@ -100,25 +109,43 @@ __global__ __launch_bounds__(256) void k_ksw_ring(Shape sh, const double *__rest
     const int k = logical % Nk, p = logical / Nk;
     const int tid = threadIdx.x;
     const bool eq = sh.equator && p == sh.npair - 1;
-    for (int q = tid; q < n; q += 256) {
+    constexpr int KJ = ksw_pix<NMAX, PLANNED>();
+    // bins (L, n - L) are empty; the loads write every other bin
+    for (int q = L + 1 + tid; q < n - L; q += 256) {
         C2 z;
         z.x = T(0);
         z.y = T(0);
         b1[rix(q)] = z;
-        b2[rix(q)] = z;
     }
-    __syncthreads();
     ksw_load_ring<T>(sh, G, p, 2 * k, eq, b1, tid);
-    ksw_load_ring<T>(sh, G, p, 2 * k + 1, eq, b2, tid);
     __syncthreads();
     fft_lds<C2, true, NMAX, PLANNED>(b1, sh, glb(tw), tid);
-    fft_lds<C2, true, NMAX, PLANNED>(b2, sh, glb(tw), tid);
+    C2 av[KJ];
+#pragma unroll
+    for (int c = 0; c < KJ; c++) {
+        const int j = tid + 256 * c;
+        if (j < n) av[c] = b1[rix(j)];
+    }
+    __syncthreads();  // every A pixel is read before the ring is reused
+    for (int q = L + 1 + tid; q < n - L; q += 256) {
+        C2 z;
+        z.x = T(0);
+        z.y = T(0);
+        b1[rix(q)] = z;
+    }
+    ksw_load_ring<T>(sh, G, p, 2 * k + 1, eq, b1, tid);
+    __syncthreads();
+    fft_lds<C2, true, NMAX, PLANNED>(b1, sh, glb(tw), tid);
     double acc = 0.0;
-    for (int j = tid; j < n; j += 256) {
-        const C2 a = b1[rix(j)];
-        const C2 b = b2[rix(j)];
-        acc += (double)a.x * (double)b.x * (double)b.x;
-        if (!eq) acc += (double)a.y * (double)b.y * (double)b.y;
+#pragma unroll
+    for (int c = 0; c < KJ; c++) {
+        const int j = tid + 256 * c;
+        if (j < n) {
+            const C2 a = av[c];
+            const C2 b = b1[rix(j)];
+            acc += (double)a.x * (double)b.x * (double)b.x;
+            if (!eq) acc += (double)a.y * (double)b.y * (double)b.y;
+        }
     }
     if (sh.alias && tid == 0) {
         const long long poff = ((long long)p * (L + 1) * sh.Cpad) * 2 + (long long)L * sh.Cpad * 2;
@@ -173,7 +200,9 @@ hipError_t ksw_ring_t(const Shape &sh, const Bufs &b, hipStream_t s)
     using C2 = typename Mt<T>::c2;
     const long long nblk = (long long)sh.npair * (sh.N / 2);
     dim3 grid((unsigned)(((nblk + 7) / 8) * 8));
-    const size_t lds = 2 * sizeof(C2) * ring_pad(sh.nphi);
+    // each thread keeps ksw_pix pixels of A: the ring must fit them
+    if (sh.nphi > 256 * ksw_pix<NMAX, PLANNED>()) return hipErrorInvalidValue;
+    const size_t lds = sizeof(C2) * ring_pad(sh.nphi);
     if (lds > 65536)
         (void)hipFuncSetAttribute((const void *)k_ksw_ring<T, NMAX, PLANNED>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

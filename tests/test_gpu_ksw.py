@@ -75,6 +75,16 @@ def test_edge_shapes(fs, orc, L, N, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("n_phi", [1536, 2500, 3072, 6144])
+def test_ring_lengths(fs, orc, n_phi, precision):
+    """Rings longer than the exact grid needs, in every register bucket of
+    the ring stage (each thread keeps its pixels of A while B is
+    transformed): planned lengths 1536, 3072, 6144 and the run-time plan
+    2500."""
+    _run(fs, orc, 48, 5, precision, n_phi=n_phi)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_medium(fs, orc, precision):
     _run(fs, orc, 256, 64, precision)
 
