@@ -252,22 +252,32 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
                 if (u0 == 0) radial_acc(32 * (c + 1), v);
             }
             const int j0 = 32 * c;
-            bool use[4];
+            // the units of a wave come in descending t, so the ones this
+            // chunk meets (t >= c with a triangular F) are a prefix of them:
+            // one branch per chunk selects a straight-line body for that many
+            int na = 0;
 #pragma unroll
-            for (int s = 0; s < 4; s++) use[s] = has[s] && (!sh.lower || j0 < 32 * ts[s] + 32);
+            for (int s = 0; s < 4; s++) na += (has[s] && (!sh.lower || j0 < 32 * ts[s] + 32)) ? 1 : 0;
+            auto chunk_mfma = [&](auto cnt) {
+                constexpr int NA = decltype(cnt)::value;
 #pragma unroll
-            for (int ks = 0; ks < 8; ks++) {
-                T bv[4];
+                for (int ks = 0; ks < 8; ks++) {
+                    T bv[4];
 #pragma unroll
-                for (int cf = 0; cf < 4; cf++) bv[cf] = nz[buf][4 * ks + k4][16 * cf + i16];
+                    for (int cf = 0; cf < 4; cf++) bv[cf] = nz[buf][4 * ks + k4][16 * cf + i16];
 #pragma unroll
-                for (int s = 0; s < 4; s++) {
-                    if (use[s]) {
+                    for (int s = 0; s < NA; s++)
 #pragma unroll
                         for (int cf = 0; cf < 4; cf++)
                             acc[s][cf] = M::mfma(af[s][ks], bv[cf], acc[s][cf]);
-                    }
                 }
+            };
+            switch (na) {
+            case 4: chunk_mfma(std::integral_constant<int, 4>{}); break;
+            case 3: chunk_mfma(std::integral_constant<int, 3>{}); break;
+            case 2: chunk_mfma(std::integral_constant<int, 2>{}); break;
+            case 1: chunk_mfma(std::integral_constant<int, 1>{}); break;
+            default: break;
             }
             if (more) {
                 if constexpr (N2) {
