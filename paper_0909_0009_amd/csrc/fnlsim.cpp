@@ -829,7 +829,7 @@ int forward_one(sim_ctx *c, const void *noise, double fnl, double2 *aT, double2 
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
     hipStream_t s = c->stream;
-    if (noise) STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s));
+    if (noise && !fnl::filter_forms_radial(sh)) STAGE(c, 0, fnl::launch_radial_lin(sh, b, noise, s));
     STAGE(c, 1, fnl::launch_filter(sh, b, noise, b.phi, s, seed));
     STAGE(c, 2, fnl::launch_synth(sh, b, b.phi, b.G, s));
     STAGE(c, 3, fnl::launch_ring(sh, b, b.G, b.F, nullptr, 0, s));
@@ -846,7 +846,7 @@ static hipError_t forward_launches(const sim_ctx *c, hipStream_t s, const void *
 {
     const Shape &sh = c->sh;
     const Bufs &b = c->b;
-    hipError_t e = fnl::launch_radial_lin(sh, b, noise, s);
+    hipError_t e = fnl::filter_forms_radial(sh) ? hipSuccess : fnl::launch_radial_lin(sh, b, noise, s);
     if (e == hipSuccess) e = fnl::launch_filter(sh, b, noise, b.phi, s);
     if (e == hipSuccess) e = fnl::launch_synth(sh, b, b.phi, b.G, s);
     if (e == hipSuccess) e = fnl::launch_ring(sh, b, b.G, b.F, nullptr, 0, s);
@@ -1171,6 +1171,8 @@ int sim_batch_create(sim_ctx *const *ctxs, int count, sim_batch **out)
         b->launches.push_back(l);
     };
     for (int stage = 0; stage < fnl::GS_COUNT; stage++) {
+        // the filter forms the radial sums with FP32 data (one precision per batch)
+        if (stage == fnl::GS_RADIAL_LIN && fnl::filter_forms_radial(ctxs[0]->sh)) continue;
         if (stage == fnl::GS_SYNTH || stage == fnl::GS_ANAL) {
             for (int cf = 5; cf >= 1; cf--) {
                 std::vector<int> mem;

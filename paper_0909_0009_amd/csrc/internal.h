@@ -154,6 +154,9 @@ hipError_t prepare_group_ring(int fp32, int nphi, int planned);
 // ----- launchers (kernels.hip); all asynchronous on `s`.
 hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s);  // seeds, lstart, cmin
 hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s);
+// true where the stored-noise filter also forms the linear radial sums
+// (FP32 data), so no launch_radial_lin is needed
+bool filter_forms_radial(const Shape &sh);
 // noise == nullptr: the noise of realization `seed` is generated in the
 // kernel (counter-based, as launch_noise writes it) instead of read, and the
 // filter also writes the linear radial sums into b.aL (launch_radial_lin's

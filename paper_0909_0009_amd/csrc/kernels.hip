@@ -103,10 +103,14 @@ template <typename T, bool SEEDED> constexpr int filter_blocks()
 }
 
 // SEEDED: the noise is generated from `seed` (seeded_noise) instead of read
-// from noise_in, and the block also forms the linear radial sums of its
-// columns, a^X_L = sum_j V^X_lj n(r_j), into aL (each noise value is then
-// generated once).
-template <typename T, bool SEEDED = false>
+// from noise_in.  RADIAL: the block also forms the linear radial sums of its
+// columns, a^X_L = sum_j V^X_lj n(r_j), into aL from the noise rows it
+// stages (each noise value is then generated or read once); the seeded
+// kernels and the FP32 stored-noise kernels do, the FP64 stored-noise one
+// leaves them to k_radial_lin (it has no registers to spare).
+template <typename T> constexpr bool filter_radial(bool seeded) { return seeded || sizeof(T) == 4; }
+
+template <typename T, bool SEEDED = false, bool RADIAL = filter_radial<T>(SEEDED)>
 __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict__ FQ_in, int Kpad,
                                             int Mpad, int nchq, const int2 *__restrict__ tiles_in,
                                             const T *__restrict__ noise_in, T *__restrict__ phi_in,
@@ -157,11 +161,11 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
 #pragma unroll
         for (int e = 0; e < 8; e++) nz[buf][sj][sc + e] = v[e];
     };
-    // seeded: per-thread FP64 partial radial sums [X][row group sj][column],
-    // each slot owned by one thread until the final reduction
-    __shared__ double rsum[SEEDED ? 2 : 1][SEEDED ? 32 : 1][SEEDED ? 64 : 1];
+    // radial sums: per-thread FP64 partials [X][row group sj][column], each
+    // slot owned by one thread until the final reduction
+    __shared__ double rsum[RADIAL ? 2 : 1][RADIAL ? 32 : 1][RADIAL ? 64 : 1];
     auto radial_acc = [&](int j0, const T (&v)[8]) {
-        if constexpr (SEEDED) {
+        if constexpr (RADIAL) {
             const int j = min(j0 + sj, N - 1);  // rows past N hold zeros
             const double vt = glb(V_in)[(long long)l * N + j];
             const double ve = glb(V_in)[(long long)(sh.L + 1 + l) * N + j];
@@ -172,7 +176,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
             }
         }
     };
-    if constexpr (SEEDED) {
+    if constexpr (RADIAL) {
 #pragma unroll
         for (int e = 0; e < 8; e++) rsum[0][sj][sc + e] = rsum[1][sj][sc + e] = 0.0;
     }
@@ -281,6 +285,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
             }
             if (more) {
                 if constexpr (N2) {
+                    if (u0 == 0) radial_acc(32 * (c + 1), v2);  // the first round stages every row
                     stage_store(buf ^ 1, v2);
 #pragma unroll
                     for (int e = 0; e < 8; e++) v2[e] = v[e];
@@ -307,7 +312,7 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
                 }
         }
     }
-    if constexpr (SEEDED) {
+    if constexpr (RADIAL) {
         __syncthreads();
         const int X = threadIdx.x >> 6, cl = threadIdx.x & 63, col = col0 + cl;
         if (X < 2 && col < ncol) {
@@ -993,7 +998,7 @@ __global__ __launch_bounds__(256, (filter_blocks<T, false>())) void g_filter(con
     const GroupItem &g = it[ord[k]];
     if (lb >= g.b.nk1) return;
     body_filter<T>(g.sh, (const T *)g.b.FQ, g.b.Kpad, g.b.Mpad, g.b.nchq, g.b.k1tiles,
-                   (const T *)g.noise, (T *)g.b.phi, 0ull, nullptr, nullptr, lb);
+                   (const T *)g.noise, (T *)g.b.phi, 0ull, g.b.V, g.b.aL, lb);
 }
 
 template <typename T, int CF>
@@ -1423,6 +1428,8 @@ hipError_t launch_filter(const Shape &sh, const Bufs &b, const void *noise, void
         filter_launch<true>(sh, b, nullptr, phi_out, s, seed);
     return hipGetLastError();
 }
+
+bool filter_forms_radial(const Shape &sh) { return sh.fp32 != 0; }
 
 hipError_t launch_radial_lin(const Shape &sh, const Bufs &b, const void *noise, hipStream_t s)
 {
