@@ -212,6 +212,18 @@ int sim_backward_seeded(sim_ctx *ctx, const unsigned long long *seeds, int R, co
 int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
                           int *nodes, double *err, double *w, void *stream);
 
+/* sim_quadrature_design with covariances shared between problems: the T and
+ * E problems of one multipole see the same C_l (Eq. cov_phi), so a design
+ * over l = 0..L and both tables needs L + 1 covariances, not 2 (L + 1).
+ *   cov     device [ncov][ntot][ntot] FP64
+ *   cidx    host [P]: problem p uses cov[cidx[p]], 0 <= cidx[p] < ncov
+ * Everything else, the result and the errors as for sim_quadrature_design
+ * (SIM_EINVAL also for a null cidx or an index out of range).  The result
+ * equals sim_quadrature_design's on the expanded [P][ntot][ntot] array. */
+int sim_quadrature_design_shared(const double *cov, int ncov, const int *cidx, const double *a,
+                                 int P, int ntot, int n, int *nodes, double *err, double *w,
+                                 void *stream);
+
 /* sim_quadrature_design without any allocation, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  The same design and kernels, with the

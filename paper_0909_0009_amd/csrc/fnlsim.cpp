@@ -1492,8 +1492,11 @@ int sim_tqu_maps(sim_ctx *c, const void *aT, const void *aE, int R, void *maps)
     return SIM_OK;
 }
 
-int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
-                          int *nodes, double *err, double *w, void *stream)
+// The allocating design: cidx (host [P], or nullptr for one covariance per
+// problem) selects each problem's covariance among ncov.
+static int quadrature_design_alloc(const double *cov, int ncov, const int *cidx, const double *a,
+                                   int P, int ntot, int n, int *nodes, double *err, double *w,
+                                   void *stream)
 {
     if (!cov || !a || !nodes || !err || !w)
         return fail(nullptr, SIM_EINVAL, "a required pointer is NULL");
@@ -1502,8 +1505,15 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
         return fail(nullptr, SIM_EINVAL, "ntot = %d outside [1, 16384]", ntot);
     if (n < 1 || n > ntot || n > fnl::kQuadMaxNodes)
         return fail(nullptr, SIM_EINVAL, "n = %d outside [1, min(ntot, %d)]", n, fnl::kQuadMaxNodes);
+    if (cidx) {
+        if (ncov < 1) return fail(nullptr, SIM_EINVAL, "ncov = %d < 1", ncov);
+        for (int p = 0; p < P; p++)
+            if (cidx[p] < 0 || cidx[p] >= ncov)
+                return fail(nullptr, SIM_EINVAL, "cidx[%d] = %d outside [0, %d)", p, cidx[p], ncov);
+    }
     hipStream_t s = (hipStream_t)stream;
-    const size_t ws_bytes = fnl::quad_workspace_bytes(P, ntot, n);
+    const bool shared = cidx != nullptr;
+    const size_t ws_bytes = fnl::quad_workspace_bytes(P, ntot, n, shared);
     // the workspace, then the device copies of the node list and error curve
     const size_t out_off = ws_bytes;
     const size_t bytes = out_off + 256 + sizeof(double) * (size_t)n + sizeof(int) * (size_t)n;
@@ -1513,15 +1523,32 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
     double *err_dev = (double *)(ws + out_off);
     int *nodes_dev = (int *)(err_dev + n);
     fnl::QuadState q{};
-    fnl::quad_bind(q, P, ntot, n, cov, a, ws);
+    fnl::quad_bind(q, P, ntot, n, cov, a, ws, shared);
     int rc = SIM_OK;
-    hipError_t e = fnl::quad_run(q, n, nodes_dev, err_dev, w, s);
+    hipError_t e = hipSuccess;
+    if (shared)
+        e = hipMemcpyAsync((void *)q.cidx, cidx, sizeof(int) * (size_t)P, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = fnl::quad_run(q, n, nodes_dev, err_dev, w, s);
     if (e == hipSuccess) e = hipMemcpyAsync(nodes, nodes_dev, sizeof(int) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(err, err_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) rc = fail(nullptr, SIM_EDEVICE, "quadrature design: %s", hipGetErrorString(e));
     (void)hipFree(ws);
     return rc;
+}
+
+int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, int n,
+                          int *nodes, double *err, double *w, void *stream)
+{
+    return quadrature_design_alloc(cov, P, nullptr, a, P, ntot, n, nodes, err, w, stream);
+}
+
+int sim_quadrature_design_shared(const double *cov, int ncov, const int *cidx, const double *a,
+                                 int P, int ntot, int n, int *nodes, double *err, double *w,
+                                 void *stream)
+{
+    if (!cidx) return fail(nullptr, SIM_EINVAL, "cidx is NULL");
+    return quadrature_design_alloc(cov, ncov, cidx, a, P, ntot, n, nodes, err, w, stream);
 }
 
 int sim_quadrature_design_noalloc(const double *cov, const double *a, int P, int ntot, int n,

@@ -23,7 +23,8 @@ constexpr size_t kQuadScratchBytes = size_t(64) << 20;
 constexpr int kQuadMaxDevices = 64;
 
 // Problem sizes and device state of one design run.  Arrays (device, FP64):
-//   C [P][ntot][ntot]  covariance of Phi on the fine grid, per problem
+//   C [ncov][ntot][ntot]  covariances of Phi on the fine grid; problem p uses
+//                      C[cidx[p]] (cidx == nullptr: C[p], ncov = P)
 //   a [P][ntot]        fine-sum weights
 //   e [P][ntot]        residual numerator b_j - v_j . z   (b = C a)
 //   d [P][ntot]        conditional variance C_jj - |v_j|^2
@@ -38,14 +39,18 @@ constexpr int kQuadMaxDevices = 64;
 struct QuadState {
     int P, ntot, nmax, npc;
     const double *C, *a;
+    const int *cidx;
     double *e, *d, *cdiag, *V, *z, *diag, *zz, *gpart, *aCa;
     unsigned char *chosen;
 };
 
 // Bytes of device workspace a design of these sizes needs, and the binding
 // of a QuadState's arrays to such a workspace (256-byte aligned base).
-size_t quad_workspace_bytes(int P, int ntot, int n);
-void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws);
+// With cidx, the binding also reserves the device copy of the index table
+// (q.cidx, P ints at the end of the workspace), which the caller fills.
+size_t quad_workspace_bytes(int P, int ntot, int n, bool shared = false);
+void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws,
+               bool shared = false);
 
 // Device address of the fixed workspace on the current device (looked up
 // once per device).

@@ -39,7 +39,8 @@ __global__ __launch_bounds__(256) void k_quad_init(QuadState q)
     const int p = blockIdx.y;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= q.ntot) return;
-    const double *Cp = q.C + (long long)p * q.ntot * q.ntot;
+    const long long cp = q.cidx ? q.cidx[p] : p;
+    const double *Cp = q.C + cp * q.ntot * q.ntot;
     const double *ap = q.a + (long long)p * q.ntot;
     // four independent partial sums keep four row loads in flight
     double b0 = 0.0, b1 = 0.0, b2 = 0.0, b3 = 0.0;
@@ -193,7 +194,8 @@ __global__ __launch_bounds__(256) void k_quad_update(QuadState q, const int *sel
         }
         for (; i < k; i++) d0 += Vp[i * n2 + j] * Vp[i * n2 + sel];
         const double dot = (d0 + d1) + (d2 + d3);
-        v = (q.C[(long long)p * n2 * n2 + (long long)sel * n2 + j] - dot) / l;
+        const long long cp = q.cidx ? q.cidx[p] : p;
+        v = (q.C[cp * n2 * n2 + (long long)sel * n2 + j] - dot) / l;
     }
     q.V[(long long)p * q.nmax * n2 + (long long)k * n2 + j] = v;
     const long long ij = (long long)p * n2 + j;
@@ -230,7 +232,7 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
 
-size_t quad_workspace_bytes(int P, int ntot, int n)
+size_t quad_workspace_bytes(int P, int ntot, int n, bool shared)
 {
     const size_t pn = (size_t)P * ntot;
     const int npc = (P + kQuadPChunk - 1) / kQuadPChunk;
@@ -239,10 +241,12 @@ size_t quad_workspace_bytes(int P, int ntot, int n)
            + align256(8 * (size_t)P * n) * 2            // z, diag
            + align256(8 * (size_t)P) * 2                // zz, aCa
            + align256(8 * (size_t)npc * ntot)           // gpart
-           + align256((size_t)ntot);                    // chosen
+           + align256((size_t)ntot)                     // chosen
+           + (shared ? align256(4 * (size_t)P) : 0);    // cidx
 }
 
-void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws)
+void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws,
+               bool shared)
 {
     const size_t pn = (size_t)P * ntot;
     q.P = P;
@@ -267,6 +271,7 @@ void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const doub
     q.aCa = (double *)take(8 * (size_t)P);
     q.gpart = (double *)take(8 * (size_t)q.npc * ntot);
     q.chosen = take((size_t)ntot);
+    q.cidx = shared ? (const int *)take(4 * (size_t)P) : nullptr;
 }
 
 hipError_t quad_scratch(void **ptr)

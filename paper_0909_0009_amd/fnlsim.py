@@ -23,6 +23,7 @@ STAGE_NAMES = ("radial_lin", "filter", "synth", "ring", "anal", "combine")
 
 EXPORTS = ("sim_init", "sim_forward", "sim_forward_seeded", "sim_noise", "sim_backward",
            "sim_backward_seeded", "sim_quadrature_design", "sim_quadrature_design_noalloc",
+           "sim_quadrature_design_shared",
            "sim_debug_stage", "sim_get_info",
            "sim_profile", "sim_profile_read",
            "sim_get_grid", "sim_batch_create", "sim_batch_forward", "sim_batch_get_mode",
@@ -79,6 +80,8 @@ def lib():
         L.sim_quadrature_design.restype = ip
         L.sim_quadrature_design_noalloc.argtypes = [vp, vp, ip, ip, ip, vp, vp, vp, vp]
         L.sim_quadrature_design_noalloc.restype = ip
+        L.sim_quadrature_design_shared.argtypes = [vp, ip, vp, vp, ip, ip, ip, vp, vp, vp, vp]
+        L.sim_quadrature_design_shared.restype = ip
         L.sim_backward_seeded.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
         L.sim_backward_seeded.restype = ip
         L.sim_backward.argtypes = [vp, vp, ip, vp, vp, vp, vp, vp]
@@ -129,26 +132,38 @@ def nlm(L):
     return (L + 1) * (L + 2) // 2
 
 
-def quadrature_design(cov, a, n, stream=None):
+def quadrature_design(cov, a, n, stream=None, cidx=None):
     """Greedy radial-quadrature design (sim_quadrature_design).
-    cov: CUDA float64 [P][ntot][ntot]; a: CUDA float64 [P][ntot].
+    cov: CUDA float64 [P][ntot][ntot]; a: CUDA float64 [P][ntot].  With cidx
+    (P integers), cov is [ncov][ntot][ntot] and problem p uses cov[cidx[p]]
+    (sim_quadrature_design_shared).
     Returns (nodes int32 [n], err float64 [n], w CUDA float64 [P][n])."""
     if cov.dtype != torch.float64 or a.dtype != torch.float64 or not cov.is_cuda or not a.is_cuda:
         raise TypeError("cov and a must be CUDA float64 tensors")
     cov = cov.contiguous()
     a = a.contiguous()
-    if cov.dim() != 3 or cov.shape[1] != cov.shape[2] or tuple(a.shape) != tuple(cov.shape[:2]):
-        raise ValueError("cov must be [P][ntot][ntot] and a [P][ntot]")
-    P, ntot = int(cov.shape[0]), int(cov.shape[1])
+    if cov.dim() != 3 or cov.shape[1] != cov.shape[2] or a.dim() != 2 or a.shape[1] != cov.shape[1]:
+        raise ValueError("cov must be [P or ncov][ntot][ntot] and a [P][ntot]")
+    P, ntot = int(a.shape[0]), int(cov.shape[1])
+    if cidx is None and int(cov.shape[0]) != P:
+        raise ValueError("without cidx, cov holds one covariance per problem")
     n = int(n)
     nodes = np.zeros(n, dtype=np.int32)
     err = np.zeros(n)
     w = torch.empty((P, n), dtype=torch.float64, device=cov.device)
     if stream is None:
         stream = torch.cuda.current_stream().cuda_stream
-    rc = lib().sim_quadrature_design(cov.data_ptr(), a.data_ptr(), P, ntot, n,
-                                     nodes.ctypes.data, err.ctypes.data, w.data_ptr(),
-                                     ctypes.c_void_p(stream) if stream else None)
+    st = ctypes.c_void_p(stream) if stream else None
+    if cidx is None:
+        rc = lib().sim_quadrature_design(cov.data_ptr(), a.data_ptr(), P, ntot, n,
+                                         nodes.ctypes.data, err.ctypes.data, w.data_ptr(), st)
+    else:
+        ci = np.ascontiguousarray(np.asarray(cidx, dtype=np.int32))
+        if ci.shape != (P,):
+            raise ValueError("cidx must hold one index per problem")
+        rc = lib().sim_quadrature_design_shared(cov.data_ptr(), int(cov.shape[0]), ci.ctypes.data,
+                                                a.data_ptr(), P, ntot, n, nodes.ctypes.data,
+                                                err.ctypes.data, w.data_ptr(), st)
     _check(rc, None)
     return nodes, err, w
 

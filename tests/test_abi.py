@@ -159,3 +159,18 @@ def test_noalloc_design_rejects_oversized_workspace_without_device(fs):
                                                 None)
     assert rc == fs.SIM_EINVAL
     assert b"workspace" in fs.lib().sim_last_error(None)
+
+
+def test_shared_design_rejects_bad_indices_without_device(fs):
+    """sim_quadrature_design_shared checks its covariance index table on the
+    host before any device call: a null table or an index outside [0, ncov)
+    is SIM_EINVAL."""
+    dummy = ctypes.c_void_p(16)
+    cidx = np.array([0, 1, 2, 1], dtype=np.int32)
+    rc = fs.lib().sim_quadrature_design_shared(dummy, 2, cidx.ctypes.data, dummy, 4, 8, 2, dummy,
+                                               dummy, dummy, None)
+    assert rc == fs.SIM_EINVAL
+    assert b"cidx[2]" in fs.lib().sim_last_error(None)
+    rc = fs.lib().sim_quadrature_design_shared(dummy, 2, None, dummy, 4, 8, 2, dummy, dummy, dummy,
+                                               None)
+    assert rc == fs.SIM_EINVAL

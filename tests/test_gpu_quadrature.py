@@ -172,3 +172,34 @@ def test_design_on_a_tight_grid(fs):
     print(f"tight grid: error floor {err[-1]:.2e}, achieved-error gap {worst:.1e}, "
           f"weights differ by {werr:.1e}", flush=True)
     assert worst <= 1e-12
+
+
+def test_shared_covariances_match_expanded(fs):
+    """sim_quadrature_design_shared: T and E problems of one multipole
+    reading one covariance through the index table give bit for bit the
+    design of the expanded one-covariance-per-problem array (the same
+    arithmetic on the same values), and the oracle's nodes."""
+    import torch
+    from oracle import quadrature as q
+    L, ntot, n = 6, 48, 12
+    r = np.linspace(13000.0, 15000.0, ntot)
+    C = inputs.covariance(L, r)
+    alpha, beta = inputs.transfer_tables(L, r)
+    dr = np.gradient(r)
+    probs, cidx = [], []
+    for l in range(2, L + 1):
+        for X in (alpha, beta):
+            x = dr * r * r * X[l]
+            s = float(x @ C[l] @ x)
+            probs.append((C[l], x / np.sqrt(s)))
+            cidx.append(l - 2)
+    cov_sh = torch.from_numpy(np.stack([C[l] for l in range(2, L + 1)])).cuda()
+    cov_ex = torch.from_numpy(np.stack([c for c, _ in probs])).cuda()
+    a = torch.from_numpy(np.stack([x for _, x in probs])).cuda()
+    n_sh, e_sh, w_sh = fs.quadrature_design(cov_sh, a, n, cidx=cidx)
+    n_ex, e_ex, w_ex = fs.quadrature_design(cov_ex, a, n)
+    assert n_sh.tolist() == n_ex.tolist()
+    assert np.array_equal(e_sh, e_ex)
+    assert torch.equal(w_sh, w_ex)
+    ref_nodes, _ = q.greedy_nodes(probs, n)
+    assert n_sh.tolist() == ref_nodes
