@@ -105,3 +105,34 @@ def test_batch_rejects_mixed_precision(fs):
     arr = (ctypes.c_void_p * 2)(a.handle.value, b.handle.value)
     h = ctypes.c_void_p()
     assert fs.lib().sim_batch_create(arr, 2, ctypes.byref(h)) == fs.SIM_EINVAL
+
+
+@pytest.mark.parametrize("form", ["grouped", "branches"])
+def test_batch_with_one_shell_ring_blocks(fs, form, monkeypatch):
+    """FP32 contexts fixed to one shell per ring block (sim_opts.ring_shells =
+    1, a shape the autotuner may pick): the grouped form's ring launches keep
+    the default two-shell blocks and the branch form runs each context's own
+    launches; both equal the sequential passes bit for bit."""
+    monkeypatch.setenv("FNLSIM_BATCH_FORM", form)
+    import torch
+    sims = []
+    for L, N in MIX[:4]:
+        p = inputs.problem(L, N)
+        sims.append(fs.Simulator(L, p["r"], p["w"], p["filter"], p["alpha"], p["beta"],
+                                 precision="fp32", ring_shells=1))
+        assert sims[-1].ring_shells == 1
+    h = _batch(fs, sims)
+    try:
+        noises = [torch.from_numpy(inputs.noise(L, N, 700 + i)).to(torch.complex64).cuda()
+                  for i, (L, N) in enumerate(MIX[:4])]
+        fnls = [40.0 + i for i in range(4)]
+        outs = [(torch.empty((1, s.n_lm), dtype=torch.complex128, device="cuda"),
+                 torch.empty((1, s.n_lm), dtype=torch.complex128, device="cuda")) for s in sims]
+        _run_batch(fs, h, noises, fnls, outs)
+        torch.cuda.synchronize()
+        for i, s in enumerate(sims):
+            rT, rE = s.forward(noises[i], fnls[i])
+            torch.cuda.synchronize()
+            assert torch.equal(rT, outs[i][0]) and torch.equal(rE, outs[i][1]), f"{form} context {i}"
+    finally:
+        fs.lib().sim_batch_destroy(h)
