@@ -14,7 +14,7 @@ namespace fnl {
 // gain there, and if chosen it gets a zero Cholesky pivot (weight 0).
 constexpr double kQuadDependent = 1e-10;
 // Problems per partial gain sum (the gain of a shell is summed over problems
-// in chunks of this many, then the chunks in order).
+// in chunks of this many, then the chunks in a fixed order).
 constexpr int kQuadPChunk = 32;
 constexpr int kQuadMaxNodes = 1024;
 // Size of the fixed device workspace behind sim_quadrature_design_noalloc

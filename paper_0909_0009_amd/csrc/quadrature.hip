@@ -81,27 +81,37 @@ __global__ __launch_bounds__(256) void k_quad_aca(QuadState q)
     }
 }
 
-// Partial gains: thread (shell j, problem chunk c) sums e_pj^2 / d_pj over the
+// Partial gains: block (64 shells, problem chunk c), 256 threads; thread
+// (shell j, quarter h) sums e_pj^2 / d_pj over the h-th quarter of the
 // chunk's problems in order (adjacent threads read adjacent shells of one
-// problem row); a dependent shell adds nothing in that problem.
-__global__ __launch_bounds__(64) void k_quad_gain(QuadState q)
+// problem row), and the four quarters are added in a fixed tree; a
+// dependent shell adds nothing in that problem.
+__global__ __launch_bounds__(256) void k_quad_gain(QuadState q)
 {
-    const int j = blockIdx.x * 64 + threadIdx.x;
+    __shared__ double part[4][64];
+    const int jl = threadIdx.x & 63, h = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + jl;
     const int c = blockIdx.y;
-    if (j >= q.ntot) return;
-    const int p1 = min(q.P, (c + 1) * kQuadPChunk);
+    constexpr int QP = kQuadPChunk / 4;
+    const int p0 = c * kQuadPChunk + h * QP;
+    const int p1 = min(q.P, p0 + QP);
     double g = 0.0;
-    for (int p = c * kQuadPChunk; p < p1; p++) {
-        const long long pj = (long long)p * q.ntot + j;
-        const double dj = q.d[pj];
-        const double ej = q.e[pj];
-        if (dj > kQuadDependent * q.cdiag[pj]) g += ej * ej / dj;
+    if (j < q.ntot) {
+        for (int p = p0; p < p1; p++) {
+            const long long pj = (long long)p * q.ntot + j;
+            const double dj = q.d[pj];
+            const double ej = q.e[pj];
+            if (dj > kQuadDependent * q.cdiag[pj]) g += ej * ej / dj;
+        }
     }
-    q.gpart[(long long)c * q.ntot + j] = g;
+    part[h][jl] = g;
+    __syncthreads();
+    if (h == 0 && j < q.ntot)
+        q.gpart[(long long)c * q.ntot + j] = (part[0][jl] + part[1][jl]) + (part[2][jl] + part[3][jl]);
 }
 
-// step k's node: the largest gain (partials summed over the chunks in order)
-// among the shells not yet chosen, the lowest index on ties (one block);
+// step k's node: the largest gain (the chunks' partials summed in a fixed
+// order) among the shells not yet chosen, the lowest index on ties (one block);
 // records it and marks it chosen
 __global__ __launch_bounds__(256) void k_quad_select(QuadState q, int *sel, int k)
 {
@@ -111,8 +121,18 @@ __global__ __launch_bounds__(256) void k_quad_select(QuadState q, int *sel, int 
     int bi = -1;
     for (int j = threadIdx.x; j < q.ntot; j += 256) {
         if (q.chosen[j]) continue;
-        double g = 0.0;
-        for (int c = 0; c < q.npc; c++) g += q.gpart[(long long)c * q.ntot + j];
+        // eight independent partial sums over the chunks (c mod 8), added in a
+        // fixed tree: eight loads in flight instead of one dependent chain
+        double s8[8] = {};
+        int c = 0;
+        for (; c + 8 <= q.npc; c += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; u++) s8[u] += q.gpart[(long long)(c + u) * q.ntot + j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++)
+            if (c + u < q.npc) s8[u] += q.gpart[(long long)(c + u) * q.ntot + j];
+        const double g = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
         if (bi < 0 || g > best) {  // j ascending: a tie keeps the lower index
             best = g;
             bi = j;
@@ -304,7 +324,7 @@ hipError_t quad_run(QuadState &q, int n, int *nodes, double *err, double *w, hip
     // among the shells not yet chosen, lowest index on ties), the pivot and
     // the error, the Cholesky column
     for (int k = 0; k < n; k++) {
-        hipLaunchKernelGGL(k_quad_gain, dim3(blocks(q.ntot, 64), q.npc), dim3(64), 0, s, q);
+        hipLaunchKernelGGL(k_quad_gain, dim3(blocks(q.ntot, 64), q.npc), dim3(256), 0, s, q);
         hipLaunchKernelGGL(k_quad_select, dim3(1), dim3(256), 0, s, q, nodes, k);
         hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, nodes, k);
         hipLaunchKernelGGL(k_quad_err, dim3(1), dim3(256), 0, s, q, err, k);
