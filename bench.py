@@ -234,10 +234,12 @@ def time_quadrature(torch, fnlsim, inputs, L=1024, ntot=400, n=70):
         best = min(best, time.perf_counter() - t0)
     del C, a
     # algorithmic bytes: each C_l read once (b = C a), then per step k the
-    # gains read (d, e, C_jj), the update reads k earlier columns, row sel of
-    # C_l (once per multipole) and (d, e), and writes column k, d and e
+    # gains read e per problem and (d, C_jj) per multipole; the update reads
+    # the k earlier columns of the multipole's factor and row sel of C_l,
+    # writes column k, updates d (per multipole) and e (per problem)
     pn = 8.0 * P * ntot
-    byts = 8.0 * (L + 1) * ntot * ntot + sum(pn * (3 + k + 0.5 + 2 + 3) for k in range(n))
+    sn = 8.0 * (L + 1) * ntot
+    byts = 8.0 * (L + 1) * ntot * ntot + sum(3 * pn + sn * (k + 6) for k in range(n))
     return {"ms": round(best * 1e3, 3), "problems": P, "fine_shells": ntot, "nodes": n,
             "algorithmic_bytes": byts, "achieved_GBps": round(byts / best / 1e9, 1),
             "final_error_rel": float(err[-1] / (err[0] + 1e-300)),

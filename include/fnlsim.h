@@ -219,7 +219,11 @@ int sim_quadrature_design(const double *cov, const double *a, int P, int ntot, i
  *   cidx    host [P]: problem p uses cov[cidx[p]], 0 <= cidx[p] < ncov
  * Everything else, the result and the errors as for sim_quadrature_design
  * (SIM_EINVAL also for a null cidx or an index out of range).  The result
- * equals sim_quadrature_design's on the expanded [P][ntot][ntot] array. */
+ * equals sim_quadrature_design's on the expanded [P][ntot][ntot] array.
+ * The Cholesky factor of the chosen nodes depends on the covariance alone, so
+ * it is formed once per distinct covariance used: the workspace is about
+ * 8 S n ntot bytes for S distinct indices in cidx, and each step reads S
+ * factors instead of P. */
 int sim_quadrature_design_shared(const double *cov, int ncov, const int *cidx, const double *a,
                                  int P, int ntot, int n, int *nodes, double *err, double *w,
                                  void *stream);

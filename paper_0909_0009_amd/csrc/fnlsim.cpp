@@ -18,6 +18,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/fnlsim.h"
@@ -1512,8 +1513,34 @@ static int quadrature_design_alloc(const double *cov, int ncov, const int *cidx,
                 return fail(nullptr, SIM_EINVAL, "cidx[%d] = %d outside [0, %d)", p, cidx[p], ncov);
     }
     hipStream_t s = (hipStream_t)stream;
-    const bool shared = cidx != nullptr;
-    const size_t ws_bytes = fnl::quad_workspace_bytes(P, ntot, n, shared);
+    // slots: the distinct covariances the problems use, in order of first
+    // use; tables pslot [P], scov [S], sstart [S + 1], sprob [P]
+    std::vector<int> tab;
+    int S = 0;
+    if (cidx) {
+        std::unordered_map<int, int> slot_of_cov;  // sized by P, not by ncov
+        std::vector<int> scov, count, pslot(P);
+        for (int p = 0; p < P; p++) {
+            auto it = slot_of_cov.emplace(cidx[p], (int)scov.size()).first;
+            if (it->second == (int)scov.size()) {
+                scov.push_back(cidx[p]);
+                count.push_back(0);
+            }
+            pslot[p] = it->second;
+            count[it->second]++;
+        }
+        S = (int)scov.size();
+        std::vector<int> sstart(S + 1, 0), sprob(P), fill(S);
+        for (int sl = 0; sl < S; sl++) sstart[sl + 1] = sstart[sl] + count[sl];
+        for (int sl = 0; sl < S; sl++) fill[sl] = sstart[sl];
+        for (int p = 0; p < P; p++) sprob[fill[pslot[p]]++] = p;
+        tab.reserve(2 * (size_t)P + 2 * (size_t)S + 1);
+        tab.insert(tab.end(), pslot.begin(), pslot.end());
+        tab.insert(tab.end(), scov.begin(), scov.end());
+        tab.insert(tab.end(), sstart.begin(), sstart.end());
+        tab.insert(tab.end(), sprob.begin(), sprob.end());
+    }
+    const size_t ws_bytes = fnl::quad_workspace_bytes(P, ntot, n, S);
     // the workspace, then the device copies of the node list and error curve
     const size_t out_off = ws_bytes;
     const size_t bytes = out_off + 256 + sizeof(double) * (size_t)n + sizeof(int) * (size_t)n;
@@ -1523,11 +1550,12 @@ static int quadrature_design_alloc(const double *cov, int ncov, const int *cidx,
     double *err_dev = (double *)(ws + out_off);
     int *nodes_dev = (int *)(err_dev + n);
     fnl::QuadState q{};
-    fnl::quad_bind(q, P, ntot, n, cov, a, ws, shared);
+    fnl::quad_bind(q, P, ntot, n, cov, a, ws, S);
     int rc = SIM_OK;
     hipError_t e = hipSuccess;
-    if (shared)
-        e = hipMemcpyAsync((void *)q.cidx, cidx, sizeof(int) * (size_t)P, hipMemcpyHostToDevice, s);
+    if (S > 0)  // the tables are contiguous from pslot on
+        e = hipMemcpyAsync((void *)q.pslot, tab.data(), sizeof(int) * tab.size(),
+                           hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = fnl::quad_run(q, n, nodes_dev, err_dev, w, s);
     if (e == hipSuccess) e = hipMemcpyAsync(nodes, nodes_dev, sizeof(int) * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipMemcpyAsync(err, err_dev, sizeof(double) * n, hipMemcpyDeviceToHost, s);

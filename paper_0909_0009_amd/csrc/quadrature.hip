@@ -9,6 +9,9 @@
 // factorisation.  Every step sums that gain over the problems for every
 // candidate shell, picks the best shell on the device, and forms one more
 // column of L for every (problem, shell) at once; the host only launches.
+// L, v and the conditional variances depend on the covariance alone, so
+// problems that share one (the T and E problems of a multipole) share them;
+// b, z and the residuals are per problem.
 //
 // On a fine grid spaced well below the correlation length the conditional
 // variances C_jj - |v_j|^2 collapse to rounding noise after a few dozen
@@ -32,6 +35,14 @@ static __device__ __align__(256) unsigned char scratch[kQuadScratchBytes];
 
 namespace {
 
+__device__ inline int slot_of(const QuadState &q, int p) { return q.pslot ? q.pslot[p] : p; }
+
+// the first problem of a slot writes the slot's per-covariance state
+__device__ inline bool slot_owner(const QuadState &q, int p, int s)
+{
+    return !q.pslot || q.sprob[q.sstart[s]] == p;
+}
+
 // b = C a (C symmetric: b_j = sum_k C_kj a_k, so adjacent threads read
 // adjacent j of row k), e = b, d = diag(C); one block per (256 shells, problem)
 __global__ __launch_bounds__(256) void k_quad_init(QuadState q)
@@ -39,7 +50,8 @@ __global__ __launch_bounds__(256) void k_quad_init(QuadState q)
     const int p = blockIdx.y;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= q.ntot) return;
-    const long long cp = q.cidx ? q.cidx[p] : p;
+    const int sl = slot_of(q, p);
+    const long long cp = q.scov ? q.scov[sl] : sl;
     const double *Cp = q.C + cp * q.ntot * q.ntot;
     const double *ap = q.a + (long long)p * q.ntot;
     // four independent partial sums keep four row loads in flight
@@ -54,8 +66,10 @@ __global__ __launch_bounds__(256) void k_quad_init(QuadState q)
     for (; k < q.ntot; k++) b0 += Cp[(long long)k * q.ntot + j] * ap[k];
     const double cjj = Cp[(long long)j * q.ntot + j];
     q.e[(long long)p * q.ntot + j] = (b0 + b1) + (b2 + b3);
-    q.d[(long long)p * q.ntot + j] = cjj;
-    q.cdiag[(long long)p * q.ntot + j] = cjj;
+    if (slot_owner(q, p, sl)) {
+        q.d[(long long)sl * q.ntot + j] = cjj;
+        q.cdiag[(long long)sl * q.ntot + j] = cjj;
+    }
     if (p == 0) q.chosen[j] = 0;
 }
 
@@ -98,10 +112,10 @@ __global__ __launch_bounds__(256) void k_quad_gain(QuadState q)
     double g = 0.0;
     if (j < q.ntot) {
         for (int p = p0; p < p1; p++) {
-            const long long pj = (long long)p * q.ntot + j;
-            const double dj = q.d[pj];
-            const double ej = q.e[pj];
-            if (dj > kQuadDependent * q.cdiag[pj]) g += ej * ej / dj;
+            const long long sj = (long long)slot_of(q, p) * q.ntot + j;
+            const double dj = q.d[sj];
+            const double ej = q.e[(long long)p * q.ntot + j];
+            if (dj > kQuadDependent * q.cdiag[sj]) g += ej * ej / dj;
         }
     }
     part[h][jl] = g;
@@ -159,18 +173,19 @@ __global__ __launch_bounds__(256) void k_quad_select(QuadState q, int *sel, int 
     }
 }
 
-// the chosen shell's pivot per problem: L_kk = sqrt(d_sel) (0 if dependent),
-// z_k = e_sel / L_kk, |z|^2 += z_k^2
+// the chosen shell's pivot per problem: L_kk = sqrt(d_sel) (0 if dependent,
+// written once per slot), z_k = e_sel / L_kk, |z|^2 += z_k^2
 __global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, const int *sels, int k)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
     if (p >= q.P) return;
-    const long long ps = (long long)p * q.ntot + sels[k];
-    const double dd = q.d[ps];
-    const double ee = q.e[ps];
-    const double l = dd > kQuadDependent * q.cdiag[ps] ? sqrt(dd) : 0.0;
+    const int sl = slot_of(q, p);
+    const long long ss = (long long)sl * q.ntot + sels[k];
+    const double dd = q.d[ss];
+    const double ee = q.e[(long long)p * q.ntot + sels[k]];
+    const double l = dd > kQuadDependent * q.cdiag[ss] ? sqrt(dd) : 0.0;
     const double zk = l > 0.0 ? ee / l : 0.0;
-    q.diag[(long long)p * q.nmax + k] = l;
+    if (slot_owner(q, p, sl)) q.diag[(long long)sl * q.nmax + k] = l;
     q.z[(long long)p * q.nmax + k] = zk;
     q.zz[p] += zk * zk;
 }
@@ -190,37 +205,44 @@ __global__ __launch_bounds__(256) void k_quad_err(QuadState q, double *err, int 
     if (threadIdx.x == 0) err[k] = part[0];
 }
 
-// column k of L for every shell j: v_j[k] = (C_j,sel - sum_{i<k} v_j[i] v_sel[i]) / l,
-// then d_j -= v_j[k]^2 and e_j -= v_j[k] z_k
+// column k of L for every shell j of a slot (one block per (256 shells,
+// slot)): v_j[k] = (C_j,sel - sum_{i<k} v_j[i] v_sel[i]) / l, then
+// d_j -= v_j[k]^2, and e_j -= v_j[k] z_k for every problem of the slot
 __global__ __launch_bounds__(256) void k_quad_update(QuadState q, const int *sels, int k)
 {
-    const int p = blockIdx.y;
+    const int sl = blockIdx.y;
     const int j = blockIdx.x * 256 + threadIdx.x;
     if (j >= q.ntot) return;
     const int sel = sels[k];
     const long long n2 = (long long)q.ntot;
-    const double *Vp = q.V + (long long)p * q.nmax * n2;
-    const double l = q.diag[(long long)p * q.nmax + k];
+    const double *Vs = q.V + (long long)sl * q.nmax * n2;
+    const double l = q.diag[(long long)sl * q.nmax + k];
     double v = 0.0;
     if (l > 0.0) {
         // four independent partial sums keep four column loads in flight
         double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
         int i = 0;
         for (; i + 4 <= k; i += 4) {
-            d0 += Vp[i * n2 + j] * Vp[i * n2 + sel];
-            d1 += Vp[(i + 1) * n2 + j] * Vp[(i + 1) * n2 + sel];
-            d2 += Vp[(i + 2) * n2 + j] * Vp[(i + 2) * n2 + sel];
-            d3 += Vp[(i + 3) * n2 + j] * Vp[(i + 3) * n2 + sel];
+            d0 += Vs[i * n2 + j] * Vs[i * n2 + sel];
+            d1 += Vs[(i + 1) * n2 + j] * Vs[(i + 1) * n2 + sel];
+            d2 += Vs[(i + 2) * n2 + j] * Vs[(i + 2) * n2 + sel];
+            d3 += Vs[(i + 3) * n2 + j] * Vs[(i + 3) * n2 + sel];
         }
-        for (; i < k; i++) d0 += Vp[i * n2 + j] * Vp[i * n2 + sel];
+        for (; i < k; i++) d0 += Vs[i * n2 + j] * Vs[i * n2 + sel];
         const double dot = (d0 + d1) + (d2 + d3);
-        const long long cp = q.cidx ? q.cidx[p] : p;
+        const long long cp = q.scov ? q.scov[sl] : sl;
         v = (q.C[cp * n2 * n2 + (long long)sel * n2 + j] - dot) / l;
     }
-    q.V[(long long)p * q.nmax * n2 + (long long)k * n2 + j] = v;
-    const long long ij = (long long)p * n2 + j;
-    q.d[ij] -= v * v;
-    q.e[ij] -= v * q.z[(long long)p * q.nmax + k];
+    q.V[(long long)sl * q.nmax * n2 + (long long)k * n2 + j] = v;
+    q.d[(long long)sl * n2 + j] -= v * v;
+    if (!q.pslot) {
+        q.e[(long long)sl * n2 + j] -= v * q.z[(long long)sl * q.nmax + k];
+        return;
+    }
+    for (int t = q.sstart[sl]; t < q.sstart[sl + 1]; t++) {
+        const int p = q.sprob[t];
+        q.e[(long long)p * n2 + j] -= v * q.z[(long long)p * q.nmax + k];
+    }
 }
 
 // optimal weights: L^T w = z by back substitution, L[i][k] = v_{node i}[k]
@@ -230,15 +252,16 @@ __global__ __launch_bounds__(64) void k_quad_weights(QuadState q, const int *nod
 {
     __shared__ double ws[kQuadMaxNodes];
     const int p = blockIdx.x, lane = threadIdx.x;
+    const int sl = slot_of(q, p);
     const long long n2 = (long long)q.ntot;
-    const double *Vp = q.V + (long long)p * q.nmax * n2;
+    const double *Vp = q.V + (long long)sl * q.nmax * n2;
     for (int k = n - 1; k >= 0; k--) {
         double s = 0.0;
         for (int i = k + 1 + lane; i < n; i += 64) s += Vp[(long long)k * n2 + nodes[i]] * ws[i];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
         if (lane == 0) {
-            const double l = q.diag[(long long)p * q.nmax + k];
+            const double l = q.diag[(long long)sl * q.nmax + k];
             ws[k] = l > 0.0 ? (q.z[(long long)p * q.nmax + k] - s) / l : 0.0;
         }
         __syncthreads();
@@ -252,27 +275,32 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
 }  // namespace
 
-size_t quad_workspace_bytes(int P, int ntot, int n, bool shared)
+size_t quad_workspace_bytes(int P, int ntot, int n, int S)
 {
-    const size_t pn = (size_t)P * ntot;
+    const int ns = S > 0 ? S : P;
+    const size_t pn = (size_t)P * ntot, sn = (size_t)ns * ntot;
     const int npc = (P + kQuadPChunk - 1) / kQuadPChunk;
-    return align256(8 * pn) * 3                        // e, d, cdiag
-           + align256(8 * pn * (size_t)n)               // V
-           + align256(8 * (size_t)P * n) * 2            // z, diag
+    return align256(8 * pn)                             // e
+           + align256(8 * sn) * 2                       // d, cdiag
+           + align256(8 * sn * (size_t)n)               // V
+           + align256(8 * (size_t)P * n)                // z
+           + align256(8 * (size_t)ns * n)               // diag
            + align256(8 * (size_t)P) * 2                // zz, aCa
            + align256(8 * (size_t)npc * ntot)           // gpart
            + align256((size_t)ntot)                     // chosen
-           + (shared ? align256(4 * (size_t)P) : 0);    // cidx
+           + (S > 0 ? align256(4 * (2 * (size_t)P + 2 * (size_t)S + 1)) : 0);  // slot tables
 }
 
 void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const double *a, void *ws,
-               bool shared)
+               int S)
 {
-    const size_t pn = (size_t)P * ntot;
+    const int ns = S > 0 ? S : P;
+    const size_t pn = (size_t)P * ntot, sn = (size_t)ns * ntot;
     q.P = P;
     q.ntot = ntot;
     q.nmax = n;
     q.npc = (P + kQuadPChunk - 1) / kQuadPChunk;
+    q.S = ns;
     q.C = C;
     q.a = a;
     unsigned char *b = static_cast<unsigned char *>(ws);
@@ -282,16 +310,24 @@ void quad_bind(QuadState &q, int P, int ntot, int n, const double *C, const doub
         return p;
     };
     q.e = (double *)take(8 * pn);
-    q.d = (double *)take(8 * pn);
-    q.cdiag = (double *)take(8 * pn);
-    q.V = (double *)take(8 * pn * (size_t)n);
+    q.d = (double *)take(8 * sn);
+    q.cdiag = (double *)take(8 * sn);
+    q.V = (double *)take(8 * sn * (size_t)n);
     q.z = (double *)take(8 * (size_t)P * n);
-    q.diag = (double *)take(8 * (size_t)P * n);
+    q.diag = (double *)take(8 * (size_t)ns * n);
     q.zz = (double *)take(8 * (size_t)P);
     q.aCa = (double *)take(8 * (size_t)P);
     q.gpart = (double *)take(8 * (size_t)q.npc * ntot);
     q.chosen = take((size_t)ntot);
-    q.cidx = shared ? (const int *)take(4 * (size_t)P) : nullptr;
+    if (S > 0) {
+        int *t = (int *)take(4 * (2 * (size_t)P + 2 * (size_t)S + 1));
+        q.pslot = t;
+        q.scov = t + P;
+        q.sstart = t + P + S;
+        q.sprob = t + P + 2 * S + 1;
+    } else {
+        q.pslot = q.scov = q.sstart = q.sprob = nullptr;
+    }
 }
 
 hipError_t quad_scratch(void **ptr)
@@ -328,7 +364,7 @@ hipError_t quad_run(QuadState &q, int n, int *nodes, double *err, double *w, hip
         hipLaunchKernelGGL(k_quad_select, dim3(1), dim3(256), 0, s, q, nodes, k);
         hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, nodes, k);
         hipLaunchKernelGGL(k_quad_err, dim3(1), dim3(256), 0, s, q, err, k);
-        hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.P), dim3(256), 0, s, q, nodes, k);
+        hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.S), dim3(256), 0, s, q, nodes, k);
     }
     hipLaunchKernelGGL(k_quad_weights, dim3(q.P), dim3(64), 0, s, q, nodes, n, w);
     return hipGetLastError();

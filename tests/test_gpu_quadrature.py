@@ -203,3 +203,27 @@ def test_shared_covariances_match_expanded(fs):
     assert torch.equal(w_sh, w_ex)
     ref_nodes, _ = q.greedy_nodes(probs, n)
     assert n_sh.tolist() == ref_nodes
+
+
+def test_shared_covariances_irregular_index(fs):
+    """An index table with unused covariances, problems of one covariance
+    spread out and unevenly many (1 to 17 per covariance), 41 problems over
+    two gain chunks and a 300-shell grid over two update blocks: bit for bit
+    the expanded design, and the oracle's nodes, errors and weights."""
+    import torch
+    ntot, n, ncov = 300, 16, 7
+    rng = np.random.default_rng(11)
+    covs = [_spd(ntot, rng) for _ in range(ncov)]
+    cidx = [int(c) for c in rng.choice([0, 2, 3, 5, 6], size=38, p=[0.4, 0.3, 0.1, 0.1, 0.1])]
+    cidx += [4, 4, 1]   # covariance 4 twice, 1 once, at the end
+    P = len(cidx)
+    probs = [(covs[c], rng.standard_normal(ntot)) for c in cidx]
+    cov_sh = torch.from_numpy(np.stack(covs)).cuda()
+    cov_ex = torch.from_numpy(np.stack([c for c, _ in probs])).cuda()
+    a = torch.from_numpy(np.stack([x for _, x in probs])).cuda()
+    n_sh, e_sh, w_sh = fs.quadrature_design(cov_sh, a, n, cidx=np.array(cidx, dtype=np.int32))
+    n_ex, e_ex, w_ex = fs.quadrature_design(cov_ex, a, n)
+    assert n_sh.tolist() == n_ex.tolist()
+    assert np.array_equal(e_sh, e_ex)
+    assert torch.equal(w_sh, w_ex)
+    _compare(fs, probs, n, f"irregular index P={P} ncov={ncov}")
