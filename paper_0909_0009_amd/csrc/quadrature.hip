@@ -99,23 +99,34 @@ __global__ __launch_bounds__(256) void k_quad_aca(QuadState q)
 // (shell j, quarter h) sums e_pj^2 / d_pj over the h-th quarter of the
 // chunk's problems in order (adjacent threads read adjacent shells of one
 // problem row), and the four quarters are added in a fixed tree; a
-// dependent shell adds nothing in that problem.
+// dependent shell adds nothing in that problem.  SH: slot tables present.
+template <bool SH>
 __global__ __launch_bounds__(256) void k_quad_gain(QuadState q)
 {
     __shared__ double part[4][64];
-    const int jl = threadIdx.x & 63, h = threadIdx.x >> 6;
+    const int jl = threadIdx.x & 63;
+    const int h = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // one per wave
     const int j = blockIdx.x * 64 + jl;
     const int c = blockIdx.y;
     constexpr int QP = kQuadPChunk / 4;
     const int p0 = c * kQuadPChunk + h * QP;
-    const int p1 = min(q.P, p0 + QP);
     double g = 0.0;
     if (j < q.ntot) {
-        for (int p = p0; p < p1; p++) {
-            const long long sj = (long long)slot_of(q, p) * q.ntot + j;
-            const double dj = q.d[sj];
-            const double ej = q.e[(long long)p * q.ntot + j];
-            if (dj > kQuadDependent * q.cdiag[sj]) g += ej * ej / dj;
+        // every problem's loads first (past the last problem they repeat it,
+        // in bounds, and add nothing), then the sum in problem order
+        double dj[QP], ej[QP], cj[QP];
+#pragma unroll
+        for (int u = 0; u < QP; u++) {
+            const int p = min(p0 + u, q.P - 1);
+            const long long sj = (long long)(SH ? q.pslot[p] : p) * q.ntot + j;
+            dj[u] = q.d[sj];
+            cj[u] = q.cdiag[sj];
+            ej[u] = q.e[(long long)p * q.ntot + j];
+        }
+#pragma unroll
+        for (int u = 0; u < QP; u++) {
+            const double t = ej[u] * ej[u] / dj[u];
+            g += (p0 + u < q.P && dj[u] > kQuadDependent * cj[u]) ? t : 0.0;
         }
     }
     part[h][jl] = g;
@@ -124,19 +135,28 @@ __global__ __launch_bounds__(256) void k_quad_gain(QuadState q)
         q.gpart[(long long)c * q.ntot + j] = (part[0][jl] + part[1][jl]) + (part[2][jl] + part[3][jl]);
 }
 
-// step k's node: the largest gain (the chunks' partials summed in a fixed
-// order) among the shells not yet chosen, the lowest index on ties (one block);
-// records it and marks it chosen
-__global__ __launch_bounds__(256) void k_quad_select(QuadState q, int *sel, int k)
+// Step k's choice, one block of kQuadChooseThreads threads:
+//  1. the node: the largest gain (each shell's chunk partials summed with
+//     eight independent partial sums, c mod 8, added in a fixed tree: eight
+//     loads in flight instead of one dependent chain) among the shells not
+//     yet chosen, the lowest index on ties; recorded and marked chosen;
+//  2. its pivot: L_kk = sqrt(d_sel) per slot (0 if dependent), and per
+//     problem z_k = e_sel / L_kk, |z|^2 += z_k^2;
+//  3. err[k] = sum_p (a^T C a - |z|^2), each thread's problems in order and
+//     then a fixed tree over the threads.
+constexpr int kQuadChooseThreads = 1024;
+
+__global__ __launch_bounds__(kQuadChooseThreads) void k_quad_choose(QuadState q, int *sel,
+                                                                     double *err, int k)
 {
-    __shared__ double gv[256];
-    __shared__ int gi[256];
+    constexpr int T = kQuadChooseThreads;
+    __shared__ double gv[T];
+    __shared__ int gi[T];
+    const int t = threadIdx.x;
     double best = 0.0;
     int bi = -1;
-    for (int j = threadIdx.x; j < q.ntot; j += 256) {
+    for (int j = t; j < q.ntot; j += T) {
         if (q.chosen[j]) continue;
-        // eight independent partial sums over the chunks (c mod 8), added in a
-        // fixed tree: eight loads in flight instead of one dependent chain
         double s8[8] = {};
         int c = 0;
         for (; c + 8 <= q.npc; c += 8) {
@@ -152,57 +172,59 @@ __global__ __launch_bounds__(256) void k_quad_select(QuadState q, int *sel, int 
             bi = j;
         }
     }
-    gv[threadIdx.x] = best;
-    gi[threadIdx.x] = bi;
+    gv[t] = best;
+    gi[t] = bi;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) {
-            const int o = gi[threadIdx.x + h], m = gi[threadIdx.x];
-            const double go = gv[threadIdx.x + h], gm = gv[threadIdx.x];
+    for (int h = T / 2; h > 0; h >>= 1) {
+        if (t < h) {
+            const int o = gi[t + h], m = gi[t];
+            const double go = gv[t + h], gm = gv[t];
             if (o >= 0 && (m < 0 || go > gm || (go == gm && o < m))) {
-                gv[threadIdx.x] = go;
-                gi[threadIdx.x] = o;
+                gv[t] = go;
+                gi[t] = o;
             }
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-        const int s = gi[0];  // n <= ntot: an unchosen shell always exists
-        sel[k] = s;
-        q.chosen[s] = 1;
+    const int sn = gi[0];  // n <= ntot: an unchosen shell always exists
+    if (t == 0) {
+        sel[k] = sn;
+        q.chosen[sn] = 1;
     }
-}
-
-// the chosen shell's pivot per problem: L_kk = sqrt(d_sel) (0 if dependent,
-// written once per slot), z_k = e_sel / L_kk, |z|^2 += z_k^2
-__global__ __launch_bounds__(256) void k_quad_pivot(QuadState q, const int *sels, int k)
-{
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= q.P) return;
-    const int sl = slot_of(q, p);
-    const long long ss = (long long)sl * q.ntot + sels[k];
-    const double dd = q.d[ss];
-    const double ee = q.e[(long long)p * q.ntot + sels[k]];
-    const double l = dd > kQuadDependent * q.cdiag[ss] ? sqrt(dd) : 0.0;
-    const double zk = l > 0.0 ? ee / l : 0.0;
-    if (slot_owner(q, p, sl)) q.diag[(long long)sl * q.nmax + k] = l;
-    q.z[(long long)p * q.nmax + k] = zk;
-    q.zz[p] += zk * zk;
-}
-
-// err[k] = sum_p (a^T C a - |z|^2) (one block, fixed order)
-__global__ __launch_bounds__(256) void k_quad_err(QuadState q, double *err, int k)
-{
-    __shared__ double part[256];
-    double s = 0.0;
-    for (int p = threadIdx.x; p < q.P; p += 256) s += q.aCa[p] - q.zz[p];
-    part[threadIdx.x] = s;
+    // each problem's z_k, then the pivot of each slot from the same d (the
+    // arrays do not overlap, so loads may run ahead of earlier stores)
+    const double *__restrict__ dv = q.d;
+    const double *__restrict__ cv = q.cdiag;
+    const double *__restrict__ ev = q.e;
+    const double *__restrict__ av = q.aCa;
+    double *__restrict__ zv = q.z;
+    double *__restrict__ zzv = q.zz;
+    double *__restrict__ lv = q.diag;
+    double es = 0.0;
+    for (int p = t; p < q.P; p += T) {
+        const long long ss = (long long)slot_of(q, p) * q.ntot + sn;
+        const double dd = dv[ss];
+        const double ee = ev[(long long)p * q.ntot + sn];
+        const double l = dd > kQuadDependent * cv[ss] ? sqrt(dd) : 0.0;
+        const double zk = l > 0.0 ? ee / l : 0.0;
+        zv[(long long)p * q.nmax + k] = zk;
+        const double zz = zzv[p] + zk * zk;
+        zzv[p] = zz;
+        es += av[p] - zz;
+    }
+    for (int sl = t; sl < q.S; sl += T) {
+        const long long ss = (long long)sl * q.ntot + sn;
+        const double dd = dv[ss];
+        lv[(long long)sl * q.nmax + k] = dd > kQuadDependent * cv[ss] ? sqrt(dd) : 0.0;
+    }
+    __syncthreads();  // every thread has read gv[0], gi[0]
+    gv[t] = es;
     __syncthreads();
-    for (int h = 128; h > 0; h >>= 1) {
-        if (threadIdx.x < h) part[threadIdx.x] += part[threadIdx.x + h];
+    for (int h = T / 2; h > 0; h >>= 1) {
+        if (t < h) gv[t] += gv[t + h];
         __syncthreads();
     }
-    if (threadIdx.x == 0) err[k] = part[0];
+    if (t == 0) err[k] = gv[0];
 }
 
 // column k of L for every shell j of a slot (one block per (256 shells,
@@ -360,10 +382,11 @@ hipError_t quad_run(QuadState &q, int n, int *nodes, double *err, double *w, hip
     // among the shells not yet chosen, lowest index on ties), the pivot and
     // the error, the Cholesky column
     for (int k = 0; k < n; k++) {
-        hipLaunchKernelGGL(k_quad_gain, dim3(blocks(q.ntot, 64), q.npc), dim3(256), 0, s, q);
-        hipLaunchKernelGGL(k_quad_select, dim3(1), dim3(256), 0, s, q, nodes, k);
-        hipLaunchKernelGGL(k_quad_pivot, dim3(blocks(q.P, 256)), dim3(256), 0, s, q, nodes, k);
-        hipLaunchKernelGGL(k_quad_err, dim3(1), dim3(256), 0, s, q, err, k);
+        if (q.pslot)
+            hipLaunchKernelGGL(k_quad_gain<true>, dim3(blocks(q.ntot, 64), q.npc), dim3(256), 0, s, q);
+        else
+            hipLaunchKernelGGL(k_quad_gain<false>, dim3(blocks(q.ntot, 64), q.npc), dim3(256), 0, s, q);
+        hipLaunchKernelGGL(k_quad_choose, dim3(1), dim3(kQuadChooseThreads), 0, s, q, nodes, err, k);
         hipLaunchKernelGGL(k_quad_update, dim3(blocks(q.ntot, 256), q.S), dim3(256), 0, s, q, nodes, k);
     }
     hipLaunchKernelGGL(k_quad_weights, dim3(q.P), dim3(64), 0, s, q, nodes, n, w);
