@@ -1134,28 +1134,40 @@ __global__ __launch_bounds__(256) void k_api_to_phi(Shape sh, const double2 *__r
 // stored (l, m >= 0) once, while the synthesis kernels weight m > 0 twice
 // (real field), so m > 0 is halved here.  For the sample mean the (0, 0)
 // entry is dropped: the derivative of the removed sky mean cancels it.
+//
+// Block = kRadAdjRows consecutive (l, m) rows, one wave per row at a time
+// (l and m wave-uniform); lane = shell, so the W loads and the (re, im)
+// stores of a row are contiguous.
+constexpr int kRadAdjRows = 16;
 template <typename T>
 __global__ __launch_bounds__(256) void k_radial_adj(Shape sh, const double *__restrict__ W,
                                                     const double2 *__restrict__ gT,
                                                     const double2 *__restrict__ gE,
                                                     T *__restrict__ out)
 {
-    const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= sh.nlm * sh.C) return;
-    const int c = (int)(t % sh.C);
-    const long long idx = t / sh.C;
-    const int l = l_of_index(idx);
-    const int m = (int)(idx - lm_index(l, 0));
-    const int s = c >> 1;
+    using C2 = typename Mt<T>::c2;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int Npad = sh.Cpad / 2;
-    const double wt = W[(long long)l * Npad + s];
-    const double we = W[(long long)(sh.L + 1 + l) * Npad + s];
-    const double2 a = gT[idx], e = gE[idx];
-    double v = (c & 1) ? wt * a.y + we * e.y : wt * a.x + we * e.x;
-    if (m == 0 && (c & 1)) v = 0.0;
-    if (m > 0) v *= 0.5;
-    if (m == 0 && l == 0 && sh.mean_mode == 0) v = 0.0;
-    out[mrow(sh.L, m, l) * sh.Cpad + c] = (T)v;
+    for (int r = w; r < kRadAdjRows; r += 4) {
+        const long long idx = (long long)blockIdx.x * kRadAdjRows + r;
+        if (idx >= sh.nlm) break;  // wave-uniform
+        const int l = __builtin_amdgcn_readfirstlane(l_of_index(idx));
+        const int m = (int)(idx - lm_index(l, 0));
+        const double2 a = gT[idx], e = gE[idx];
+        // m > 0 halved; Im of m = 0 is zero; (0, 0) dropped for the sample mean
+        const double h = (m == 0 && l == 0 && sh.mean_mode == 0) ? 0.0 : m > 0 ? 0.5 : 1.0;
+        const double hi = m > 0 ? 0.5 : 0.0;
+        const double *Wt = W + (long long)l * Npad;
+        const double *We = W + (long long)(sh.L + 1 + l) * Npad;
+        C2 *dst = reinterpret_cast<C2 *>(out + mrow(sh.L, m, l) * sh.Cpad);
+        for (int s = lane; s < sh.N; s += 64) {
+            const double wt = Wt[s], we = We[s];
+            C2 v;
+            v.x = (T)(h * (wt * a.x + we * e.x));
+            v.y = (T)(hi * (wt * a.y + we * e.y));
+            dst[s] = v;
+        }
+    }
 }
 
 // Reverse ring stage, block = (ring pair, shell).  Both the Phi_L map (from
@@ -1362,27 +1374,40 @@ __global__ __launch_bounds__(256) void k_filter_t(Shape sh, const T *__restrict_
 }
 
 // dLoss/df_NL = sum over ring blocks (fixed order), minus the ensemble-mean
-// term sum_s sqrt(4 pi) <Phi_L^2>(r_s) Re(sum_X W^X_0s abar^X_00).
-__global__ __launch_bounds__(256) void k_fbar(Shape sh, const double *__restrict__ fpart,
-                                              const double *__restrict__ W,
-                                              const double *__restrict__ mu,
-                                              const double2 *__restrict__ gT,
-                                              const double2 *__restrict__ gE,
-                                              double *__restrict__ out)
+// term sum_s sqrt(4 pi) <Phi_L^2>(r_s) Re(sum_X W^X_0s abar^X_00).  One block
+// of 1024 threads; each thread keeps eight independent partial sums (entry
+// q goes to sum (q / 1024) mod 8), added in a fixed tree, so eight loads are
+// in flight instead of one dependent chain.
+constexpr int kFbarThreads = 1024;
+__global__ __launch_bounds__(kFbarThreads) void k_fbar(Shape sh, const double *__restrict__ fpart,
+                                                       const double *__restrict__ W,
+                                                       const double *__restrict__ mu,
+                                                       const double2 *__restrict__ gT,
+                                                       const double2 *__restrict__ gE,
+                                                       double *__restrict__ out)
 {
-    __shared__ double red[256];
+    constexpr int T = kFbarThreads;
+    __shared__ double red[T];
     const int tid = threadIdx.x;
     const long long n = (long long)sh.npair * sh.N;
-    double acc = 0.0;
-    for (long long q = tid; q < n; q += 256) acc += fpart[q];
+    double s8[8] = {};
+    long long q = tid;
+    for (; q + 7 * T < n; q += 8 * T) {
+#pragma unroll
+        for (int u = 0; u < 8; u++) s8[u] += fpart[q + (long long)u * T];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; u++)
+        if (q + (long long)u * T < n) s8[u] += fpart[q + (long long)u * T];
+    double acc = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
     if (sh.mean_mode == 1) {
         const int Npad = sh.Cpad / 2;
-        for (int s = tid; s < sh.N; s += 256)
+        for (int s = tid; s < sh.N; s += T)
             acc -= mu[s] * (W[s] * gT[0].x + W[(long long)(sh.L + 1) * Npad + s] * gE[0].x);
     }
     red[tid] = acc;
     __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
+    for (int w = T / 2; w > 0; w >>= 1) {
         if (tid < w) red[tid] += red[tid + w];
         __syncthreads();
     }
@@ -1623,7 +1648,7 @@ hipError_t launch_api_to_phi(const Shape &sh, const double2 *api, void *phi, hip
 hipError_t launch_radial_adj(const Shape &sh, const Bufs &b, const double2 *gT, const double2 *gE,
                              void *out, hipStream_t s)
 {
-    dim3 grid(blocks_for(sh.nlm * sh.C, 256));
+    dim3 grid(blocks_for(sh.nlm, kRadAdjRows));
     if (sh.fp32)
         hipLaunchKernelGGL(k_radial_adj<float>, grid, dim3(256), 0, s, sh, b.W, gT, gE, (float *)out);
     else
@@ -1691,7 +1716,7 @@ hipError_t launch_filter_t(const Shape &sh, const Bufs &b, const void *phibar, v
 hipError_t launch_fbar(const Shape &sh, const Bufs &b, const double *fpart, const double2 *gT,
                        const double2 *gE, double *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fbar, dim3(1), dim3(256), 0, s, sh, fpart, b.W, b.mu, gT, gE, out);
+    hipLaunchKernelGGL(k_fbar, dim3(1), dim3(kFbarThreads), 0, s, sh, fpart, b.W, b.mu, gT, gE, out);
     return hipGetLastError();
 }
 
