@@ -281,7 +281,7 @@ __global__ __launch_bounds__(64, (anal_bf_waves<CF, NP>())) void k_anal_bf(
     const int nchunk = (npair + PC - 1) / PC;
     const int lend = l0w + RW - 1;
     const int fend = min(NF, (L - l0w) / 32 + 1);
-    for (int pc = 0; pc < nchunk; pc++) {
+    for (int pc = nchunk - 1; pc >= 0; pc--) {  // equator first, as in k_anal
         const int cm = cmin[(long long)m * nchunk + pc];
         if (cm > lend) continue;  // wave-uniform
         const int f0 = cm <= l0w + 31 ? 0 : (cm - l0w - 31 + 31) / 32;
@@ -365,7 +365,7 @@ template <int CF, int NP>
 void synth_bf_t(const Shape &sh, const Bufs &b, void *G, hipStream_t s)
 {
     hipLaunchKernelGGL((k_synth_bf<CF, NP>), dim3((unsigned)b.nk2), dim3(64), 0, s, sh, b.k2tiles, b.x,
-                       b.seed, b.seedoff, b.lstart, b.coef, (const __bf16 *)b.phib, (float *)G);
+                       b.seed, b.seedoff, b.lstart_mat, b.coef, (const __bf16 *)b.phib, (float *)G);
 }
 
 template <int NP>

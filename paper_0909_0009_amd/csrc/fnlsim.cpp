@@ -638,6 +638,11 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
         b.seed = (double2 *)p;
         if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * np))) goto bad;
         b.lstart = (int *)p;
+        b.lstart_mat = b.lstart;
+        if (sh.fp32) {
+            if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * np))) goto bad;
+            b.lstart_mat = (int *)p;
+        }
         if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 31) / 32)))) goto bad;
         b.cmin = (int *)p;
         if (sh.npiece) {

@@ -12,6 +12,12 @@ constexpr int kMaxPhi = 8192;   // longest ring the in-LDS FFT handles
 constexpr int kMaxPasses = 16;
 constexpr int kSeedStride = 32; // l spacing of stored recurrence seeds
 constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (polar skip)
+// Polar skip of the Legendre contractions with FP32 data: the terms left out
+// before the first |lambda_lm(x_p)| above this are below FP32 rounding by
+// more than four orders of magnitude (unit roundoff 6e-8).  The FP64 path
+// and the spin-2 maps (whose functions near the pole exceed lambda_lm by
+// up to l^2 / sin^2 theta) keep kLambdaTiny.
+constexpr double kLambdaTinyF32 = 1e-12;
 constexpr int kCoefPad = 128;      // zero rows after each m's coefficient block (>= analysis rows per block)
 constexpr int kPhiPad = 32;        // zero rows after the last m block of the Phi matrices (synthesis prefetch)
 // Work of one Legendre wave: ring pairs per synthesis wave and l rows per
@@ -93,7 +99,9 @@ struct Bufs {
                        // entering l0 = m + 32u ((0, lambda_mm) for u = 0)
     int *seedoff;      // [L+2] first seed row of each m
     int *lstart;       // [L+1][npair] first l with |lambda_lm(x_p)| > 1e-30 (L+1 if none)
-    int *cmin;         // [L+1][ceil(npair/32)] min of lstart over each 32-pair chunk
+    int *lstart_mat;   // the same for the matrix-core contractions: threshold
+                       // kLambdaTinyF32 with FP32 data, else lstart itself
+    int *cmin;         // [L+1][ceil(npair/32)] min of lstart_mat over each 32-pair chunk
     int2 *k1tiles;     // [nk1] (l, column tile) of each filter workgroup
     int4 *k2tiles;     // [nk2] synthesis blocks (m, pair tile, column tile, 0)
     int4 *k4tiles;     // [nk4] analysis blocks (m, l tile, column tile, 0)

@@ -416,7 +416,8 @@ template <typename T> constexpr int synth_ld() { return sizeof(T) == 8 ? 36 : 72
 // into the MFMA A layout (lane = (pair, k-slot)), so every recurrence step
 // feeds NF = PW/16 pair fragments x 2 parities x CF column fragments of
 // MFMAs.  The wave starts at the first stored state below the first l where
-// any of its pairs has |lambda_lm| > 1e-30 (polar skip).
+// any of its pairs has |lambda_lm| above the polar-skip threshold (1e-30,
+// 1e-12 with FP32 data).
 template <typename T, int CF>
 __device__ __forceinline__ void body_synth(const Shape &sh, const int4 *__restrict__ tiles_in,
                                            const double *__restrict__ x_in,
@@ -743,8 +744,8 @@ static_assert(kCoefPad >= anal_rw<float>() && kCoefPad >= anal_rw<double>(), "co
 // FP64 recurrence over rows [h RW/2, (h+1) RW/2) of pair q from the stored
 // state, writes the values to an LDS tile, and the wave reads them back in the
 // MFMA A layout (lane = (row, pair)).  Chunks and fragments whose rows all lie
-// below the first l where any pair of the chunk has |lambda| > 1e-30 are
-// skipped (polar skip).  mode 0 folds the radial sum into the epilogue:
+// below the first l where any pair of the chunk has |lambda| above the
+// polar-skip threshold (1e-30, 1e-12 with FP32 data) are skipped.  mode 0 folds the radial sum into the epilogue:
 // part[ct][X][idx(l, m)] = sum_s W^X_ls Phi_NL,lm(s) over the tile's shells;
 // mode 1 writes Phi_NL per shell; mode 2 (reverse pass) writes the per-shell
 // output plus the direct cotangent sum_X W^X_ls abar^X_lm, no mean handling.
@@ -809,7 +810,10 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     const int lend = l0w + RW - 1;
     // fragments holding a row l <= L (fragment f covers rows l0w + 32 f ..)
     const int fend = min(NF, (L - l0w) / 32 + 1);
-    for (int pc = 0; pc < nchunk; pc++) {
+    // equator first: every l tile of an (m, column tile) group starts at the
+    // last chunk, so tiles that run together read the same F lines; the ones
+    // with polar chunks to skip finish early instead of starting late
+    for (int pc = nchunk - 1; pc >= 0; pc--) {
         const int cm = cmin[(long long)m * nchunk + pc];
         if (cm > lend) continue;  // wave-uniform
         // first fragment with a row at or above cm
@@ -1010,7 +1014,7 @@ __global__ __launch_bounds__(64, synth_waves<T>()) void g_synth(const GroupItem 
     const int k = group_find(off, n, blockIdx.x, lb);
     const GroupItem &g = it[ord[k]];
     if (lb >= g.b.nk2) return;
-    body_synth<T, CF>(g.sh, g.b.k2tiles, g.b.x, g.b.seed, g.b.seedoff, g.b.lstart, g.b.coef,
+    body_synth<T, CF>(g.sh, g.b.k2tiles, g.b.x, g.b.seed, g.b.seedoff, g.b.lstart_mat, g.b.coef,
                       (const T *)g.b.phi, (T *)g.b.G, lb);
 }
 
@@ -1054,13 +1058,15 @@ __global__ __launch_bounds__(256) void g_combine(const GroupItem *__restrict__ i
 
 // One thread per (m, pair): run lambda_lm(x_p) up l, store the recurrence
 // state (lambda_{l0-1}, lambda_{l0-2}) entering every l0 = m + 32 u, and the
-// first l where |lambda_lm| exceeds 1e-30.
+// first l where |lambda_lm| exceeds 1e-30 (lstart) and where it exceeds
+// tiny_mat (lstart_mat, written only when it is a separate table).
 __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__restrict__ x,
                                                    const double *__restrict__ lmm,
                                                    const double2 *__restrict__ coef,
                                                    const int *__restrict__ seedoff,
                                                    double2 *__restrict__ seed,
-                                                   int *__restrict__ lstart)
+                                                   int *__restrict__ lstart,
+                                                   int *__restrict__ lstart_mat, double tiny_mat)
 {
     const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     const int npair = sh.npair, L = sh.L;
@@ -1068,7 +1074,7 @@ __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__res
     const int p = (int)(t % npair), m = (int)(t / npair);
     const double xp = x[p];
     double l1 = 0.0, l2 = lmm[(long long)m * npair + p];
-    int first = L + 1;
+    int first = L + 1, first_mat = L + 1;
     for (int l = m; l <= L; l++) {
         const int d = l - m;
         if (d % kSeedStride == 0)
@@ -1076,10 +1082,12 @@ __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__res
         const double2 ab = coef[crow(L, m) + d];
         const double v = ab.x * xp * l1 - ab.y * l2;
         if (first > L && fabs(v) > kLambdaTiny) first = l;
+        if (first_mat > L && fabs(v) > tiny_mat) first_mat = l;
         l2 = l1;
         l1 = v;
     }
     lstart[(long long)m * npair + p] = first;
+    if (lstart_mat != lstart) lstart_mat[(long long)m * npair + p] = first_mat;
 }
 
 __global__ __launch_bounds__(256) void k_chunk_min(Shape sh, const int *__restrict__ lstart,
@@ -1422,9 +1430,10 @@ hipError_t launch_seed_init(const Shape &sh, const Bufs &b, hipStream_t s)
 {
     const long long n = (long long)(sh.L + 1) * sh.npair;
     hipLaunchKernelGGL(k_seed_init, dim3(blocks_for(n, 256)), dim3(256), 0, s, sh, b.x, b.lmm,
-                       b.coef, b.seedoff, b.seed, b.lstart);
+                       b.coef, b.seedoff, b.seed, b.lstart, b.lstart_mat,
+                       sh.fp32 ? kLambdaTinyF32 : kLambdaTiny);
     const long long nc = (long long)(sh.L + 1) * ((sh.npair + kAnalPC - 1) / kAnalPC);
-    hipLaunchKernelGGL(k_chunk_min, dim3(blocks_for(nc, 256)), dim3(256), 0, s, sh, b.lstart,
+    hipLaunchKernelGGL(k_chunk_min, dim3(blocks_for(nc, 256)), dim3(256), 0, s, sh, b.lstart_mat,
                        b.cmin);
     return hipGetLastError();
 }
@@ -1485,7 +1494,7 @@ static void synth_t(const Shape &sh, const Bufs &b, const void *phi, void *G, hi
 {
     dim3 grid((unsigned)b.nk2);
     hipLaunchKernelGGL((k_synth<T, CF>), grid, dim3(64), 0, s, sh, b.k2tiles, b.x, b.seed,
-                       b.seedoff, b.lstart, b.coef, (const T *)phi, (T *)G);
+                       b.seedoff, b.lstart_mat, b.coef, (const T *)phi, (T *)G);
 }
 
 template <typename T>
