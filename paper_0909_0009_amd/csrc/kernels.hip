@@ -161,24 +161,31 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
 #pragma unroll
         for (int e = 0; e < 8; e++) nz[buf][sj][sc + e] = v[e];
     };
-    // radial sums: per-thread FP64 partials [X][row group sj][column], each
-    // slot owned by one thread until the final reduction
-    __shared__ double rsum[RADIAL ? 2 : 1][RADIAL ? 32 : 1][RADIAL ? 64 : 1];
+    // radial sums: per-thread FP64 partials, slot [X][e / 2][thread] holding
+    // columns sc + e, sc + e + 1 of row group sj, each owned by one thread
+    // until the final reduction.  Thread-minor, so a wave's 16-byte accesses
+    // are 1 KB contiguous (no bank conflicts).
+    __shared__ double2 rsum[RADIAL ? 2 : 1][RADIAL ? 4 : 1][RADIAL ? 256 : 1];
     auto radial_acc = [&](int j0, const T (&v)[8]) {
         if constexpr (RADIAL) {
             const int j = min(j0 + sj, N - 1);  // rows past N hold zeros
             const double vt = glb(V_in)[(long long)l * N + j];
             const double ve = glb(V_in)[(long long)(sh.L + 1 + l) * N + j];
 #pragma unroll
-            for (int e = 0; e < 8; e++) {
-                rsum[0][sj][sc + e] += vt * (double)v[e];
-                rsum[1][sj][sc + e] += ve * (double)v[e];
+            for (int h = 0; h < 4; h++) {
+                double2 a = rsum[0][h][threadIdx.x], b = rsum[1][h][threadIdx.x];
+                a.x += vt * (double)v[2 * h];
+                a.y += vt * (double)v[2 * h + 1];
+                b.x += ve * (double)v[2 * h];
+                b.y += ve * (double)v[2 * h + 1];
+                rsum[0][h][threadIdx.x] = a;
+                rsum[1][h][threadIdx.x] = b;
             }
         }
     };
     if constexpr (RADIAL) {
 #pragma unroll
-        for (int e = 0; e < 8; e++) rsum[0][sj][sc + e] = rsum[1][sj][sc + e] = 0.0;
+        for (int h = 0; h < 4; h++) rsum[0][h][threadIdx.x] = rsum[1][h][threadIdx.x] = double2{0.0, 0.0};
     }
 
     // Work unit: a 16-row half tile (t, h).  Units are numbered by descending
@@ -316,8 +323,13 @@ __device__ __forceinline__ void body_filter(const Shape &sh, const T *__restrict
         __syncthreads();
         const int X = threadIdx.x >> 6, cl = threadIdx.x & 63, col = col0 + cl;
         if (X < 2 && col < ncol) {
+            // column cl of row group g: thread 8 g + cl / 8, element cl % 8
+            const int h = (cl & 7) >> 1, odd = cl & 1, q = cl >> 3;
             double a = 0.0;
-            for (int g = 0; g < 32; g++) a += rsum[X][g][cl];
+            for (int g = 0; g < 32; g++) {
+                const double2 r = rsum[X][h][8 * g + q];
+                a += odd ? r.y : r.x;
+            }
             reinterpret_cast<GLB double *>(glb(aL_in))[2 * (X * nlm + base / 2 + col / 2) + (col & 1)] = a;
         }
     }
