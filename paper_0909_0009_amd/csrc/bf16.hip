@@ -282,7 +282,7 @@ __global__ __launch_bounds__(64, (anal_bf_waves<CF, NP>())) void k_anal_bf(
     const int lend = l0w + RW - 1;
     const int fend = min(NF, (L - l0w) / 32 + 1);
     for (int pc = nchunk - 1; pc >= 0; pc--) {  // equator first, as in k_anal
-        const int cm = cmin[(long long)m * nchunk + pc];
+        const int cm = cmin[((long long)m * nchunk + pc) * kCminW];
         if (cm > lend) continue;  // wave-uniform
         const int f0 = cm <= l0w + 31 ? 0 : (cm - l0w - 31 + 31) / 32;
         // B: (E, O) of ring pairs pc*32 + 8 k4 + j, j < 8, per column fragment;

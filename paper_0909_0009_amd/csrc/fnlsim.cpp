@@ -643,7 +643,7 @@ int init_ctx(sim_ctx **out, int lmax, int nshell, const double *r, const double 
             if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * np))) goto bad;
             b.lstart_mat = (int *)p;
         }
-        if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 31) / 32)))) goto bad;
+        if ((rc = alloc_zero(c, &p, sizeof(int) * (size_t)(L + 1) * ((np + 31) / 32) * fnl::kCminW))) goto bad;
         b.cmin = (int *)p;
         if (sh.npiece) {
             if ((rc = alloc_zero(c, &p, (size_t)2 * (b.nseedrow + 2) * sh.Cpad * 2 * sh.npiece * 16)))

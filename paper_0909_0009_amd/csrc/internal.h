@@ -18,6 +18,7 @@ constexpr double kLambdaTiny = 1e-30;  // |lambda| below this is treated as 0 (p
 // and the spin-2 maps (whose functions near the pole exceed lambda_lm by
 // up to l^2 / sin^2 theta) keep kLambdaTiny.
 constexpr double kLambdaTinyF32 = 1e-12;
+constexpr int kCminW = 9;  // polar-start entries per analysis chunk: the chunk, its 8 K-steps
 constexpr int kCoefPad = 128;      // zero rows after each m's coefficient block (>= analysis rows per block)
 constexpr int kPhiPad = 32;        // zero rows after the last m block of the Phi matrices (synthesis prefetch)
 // Work of one Legendre wave: ring pairs per synthesis wave and l rows per
@@ -101,7 +102,8 @@ struct Bufs {
     int *lstart;       // [L+1][npair] first l with |lambda_lm(x_p)| > 1e-30 (L+1 if none)
     int *lstart_mat;   // the same for the matrix-core contractions: threshold
                        // kLambdaTinyF32 with FP32 data, else lstart itself
-    int *cmin;         // [L+1][ceil(npair/32)] min of lstart_mat over each 32-pair chunk
+    int *cmin;         // [L+1][ceil(npair/32)][kCminW]: min of lstart_mat over each 32-pair
+                       // chunk, then over each of its eight 4-pair K-steps
     int2 *k1tiles;     // [nk1] (l, column tile) of each filter workgroup
     int4 *k2tiles;     // [nk2] synthesis blocks (m, pair tile, column tile, 0)
     int4 *k4tiles;     // [nk4] analysis blocks (m, l tile, column tile, 0)

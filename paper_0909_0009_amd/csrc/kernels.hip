@@ -826,10 +826,9 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
     // last chunk, so tiles that run together read the same F lines; the ones
     // with polar chunks to skip finish early instead of starting late
     for (int pc = nchunk - 1; pc >= 0; pc--) {
-        const int cm = cmin[(long long)m * nchunk + pc];
+        const auto cmc = cmin + ((long long)m * nchunk + pc) * kCminW;
+        const int cm = cmc[0];
         if (cm > lend) continue;  // wave-uniform
-        // first fragment with a row at or above cm
-        const int f0 = cm <= l0w + 31 ? 0 : (cm - l0w - 31 + 31) / 32;
         // B operands F_{E/O}[pair][column] of a K-step (4 pairs); pairs past
         // the last one read the next m (or the zero padding after the last m)
         // and meet lambda = 0 exactly
@@ -870,7 +869,11 @@ __device__ __forceinline__ void body_anal(const Shape &sh, const int4 *__restric
             }
         }
         __syncthreads();
+        // per K-step polar start: the first fragment with a row at or above
+        // the first l where any of the K-step's 4 pairs exceeds the threshold
         auto kstep = [&](int kk, const T *E, const T *O) {
+            const int ck = cmc[1 + kk];
+            const int f0 = ck <= l0w + 31 ? 0 : (ck - l0w) / 32;
 #pragma unroll
             for (int f = 0; f < NF; f++) {
                 if (f >= f0 && f < fend) {
@@ -1102,6 +1105,10 @@ __global__ __launch_bounds__(256) void k_seed_init(Shape sh, const double *__res
     if (lstart_mat != lstart) lstart_mat[(long long)m * npair + p] = first_mat;
 }
 
+static_assert(kCminW == 1 + kAnalPC / 4, "one polar-start entry per chunk and per K-step");
+
+// One thread per (m, 32-pair chunk): the first l where any pair of the chunk
+// has |lambda_lm| above the threshold, then the same for each 4-pair K-step.
 __global__ __launch_bounds__(256) void k_chunk_min(Shape sh, const int *__restrict__ lstart,
                                                    int *__restrict__ cmin)
 {
@@ -1110,9 +1117,14 @@ __global__ __launch_bounds__(256) void k_chunk_min(Shape sh, const int *__restri
     if (t >= (long long)(sh.L + 1) * nchunk) return;
     const int c = (int)(t % nchunk), m = (int)(t / nchunk);
     int v = sh.L + 1;
-    for (int p = c * kAnalPC; p < min(sh.npair, c * kAnalPC + kAnalPC); p++)
-        v = min(v, lstart[(long long)m * sh.npair + p]);
-    cmin[t] = v;
+    for (int k = 0; k < kAnalPC / 4; k++) {
+        int vk = sh.L + 1;
+        for (int p = c * kAnalPC + 4 * k; p < min(sh.npair, c * kAnalPC + 4 * k + 4); p++)
+            vk = min(vk, lstart[(long long)m * sh.npair + p]);
+        cmin[t * kCminW + 1 + k] = vk;
+        v = min(v, vk);
+    }
+    cmin[t * kCminW] = v;
 }
 
 // ---------------------------------------------------------- layout helpers
