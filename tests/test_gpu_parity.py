@@ -140,6 +140,51 @@ def test_edge_shapes_fp64(fs, orc, L, N, nring, nphi, mean, R):
         _check_all([g[k] for g in got], ref, L, TOL["fp64"], f"edge L={L} N={N} r={k}")
 
 
+# the same shapes on the FP32 path (noise rounded to FP32 on both sides):
+# ragged tiles, padded columns, N > 256 and the smallest l range, where the
+# FP32 polar-skip threshold and the per-K-step polar start decide tile edges
+@pytest.mark.parametrize("L,N,nring,nphi,mean,R", EDGE)
+def test_edge_shapes_fp32(fs, orc, L, N, nring, nphi, mean, R):
+    p = _problem(L, N)
+    sim = _sim(fs, p, L, "fp32", n_ring=nring, n_phi=nphi,
+               mean="ensemble" if mean else "sample")
+    noises = [inputs.noise(L, N, 5000 + k).astype(np.complex64).astype(np.complex128)
+              for k in range(R)]
+    fnl = [30.0 + 10 * k for k in range(R)]
+    import torch
+    batch = torch.from_numpy(np.stack(noises)).to(torch.complex64).cuda()
+    got = sim.forward(batch, fnl, want_nl=True)
+    P = _oracle(orc, p, L, mean=mean)
+    for k in range(R):
+        ref = P.forward(noises[k], fnl[k])
+        _check_all([g[k] for g in got], ref, L, TOL["fp32"], f"edge fp32 L={L} N={N} r={k}")
+
+
+def test_forward_rejects_empty_and_null_then_still_runs(fs, orc):
+    """R = 0 and null outputs are SIM_EINVAL through the C ABI, with no device
+    work; the context then still gives the oracle's result."""
+    import torch
+    L, N = 8, 3
+    p = _problem(L, N)
+    sim = _sim(fs, p, L, "fp64")
+    noise = inputs.noise(L, N, 77)
+    x = torch.from_numpy(noise[None]).cuda()
+    f = np.array([40.0])
+    aT = torch.empty((1, sim.n_lm), dtype=torch.complex128, device="cuda")
+    aE = torch.empty_like(aT)
+    lib = fs.lib()
+    assert lib.sim_forward(sim._h, x.data_ptr(), 0, f.ctypes.data, aT.data_ptr(), aE.data_ptr(),
+                           None, None) == fs.SIM_EINVAL
+    assert lib.sim_forward(sim._h, x.data_ptr(), 1, f.ctypes.data, None, aE.data_ptr(),
+                           None, None) == fs.SIM_EINVAL
+    assert lib.sim_forward(sim._h, None, 1, f.ctypes.data, aT.data_ptr(), aE.data_ptr(),
+                           None, None) == fs.SIM_EINVAL
+    assert lib.sim_last_error(sim._h)  # the reason is reported
+    got = sim.forward(x, 40.0, want_nl=True)
+    ref = _oracle(orc, p, L).forward(noise, 40.0)
+    _check_all([g[0] for g in got], ref, L, TOL["fp64"], "after rejected calls")
+
+
 # Paper workload: 200 nodes = 400 real columns in five 80-column tiles of the
 # Legendre kernels (40 shells each); one kept shell per tile, the last one
 # included.
